@@ -1,0 +1,180 @@
+"""CPU oracle for the bandwidth-limited BLAS-1/2 operations of Rupp et al.,
+"Performance Portability Study of Linear Algebra Kernels in OpenCL" (IWOCL 2014).
+
+TEST INFRASTRUCTURE ONLY.  The functions here are the parity reference that the
+GPU library is checked against.  They share no code with the GPU path and the
+GPU path never imports them; only the tests, the smoke check and the benchmark's
+CPU-baseline leg do.
+
+Every function takes numpy float64 arrays holding the exact stored values of
+the operands (f32 and bf16 operands widened exactly) and returns float64
+arrays.  The arithmetic lives in ``oracle.c`` (plain C, double precision,
+compiled with ``-ffp-contract=off``); this module only marshals arguments.
+Operation definitions follow Section 2 of the paper:
+
+* ``copy``   x <- y
+* ``axpby``  x <- alpha*y + beta*z        (rounding sequence RN(alpha*y + RN(beta*z)))
+* ``dot``    <x, y>                       (Dot2 compensated evaluation)
+* ``nrm2``   sqrt(<x, x>)
+* ``gemv``   y <- op(A) x, row- or column-major A
+* ``ger``    A <- u v^T                   (gradient of y = A x with respect to A)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+F64, F32, BF16 = 0, 1, 2
+ROW_MAJOR, COL_MAJOR = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc (no GPU code)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64, c_int, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.o_round_bf16.argtypes = [dbl]
+    lib.o_round_bf16.restype = dbl
+    lib.o_scalar.argtypes = [c_int, dbl, c_int, dbl]
+    lib.o_scalar.restype = dbl
+    lib.o_copy.argtypes = [i64, dp, dp]
+    lib.o_copy.restype = None
+    lib.o_axpby.argtypes = [c_int, i64, dbl, dp, dbl, dp, dp]
+    lib.o_axpby.restype = None
+    lib.o_dot.argtypes = [i64, dp, i64, dp, i64]
+    lib.o_dot.restype = dbl
+    lib.o_nrm2.argtypes = [i64, dp]
+    lib.o_nrm2.restype = dbl
+    lib.o_gemv.argtypes = [c_int, c_int, i64, i64, dp, i64, dp, dp]
+    lib.o_gemv.restype = None
+    lib.o_ger.argtypes = [c_int, c_int, i64, i64, dp, dp, dp, i64]
+    lib.o_ger.restype = None
+    _lib = lib
+    return lib
+
+
+def _arr(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+
+
+def prec_code(p) -> int:
+    return _PREC[p]
+
+
+def round_bf16(v: float) -> float:
+    """Round an f32 value to bf16, nearest-even (NaN stays quiet NaN)."""
+    return _load().o_round_bf16(float(v))
+
+
+def scalar(prec, host: float, dev: float | None = None) -> float:
+    """Effective scaling factor in the compute precision of ``prec``."""
+    return _load().o_scalar(prec_code(prec), float(host), int(dev is not None),
+                            0.0 if dev is None else float(dev))
+
+
+def copy(y) -> np.ndarray:
+    y = _arr(y)
+    x = np.empty_like(y)
+    _load().o_copy(y.size, _ptr(y), _ptr(x))
+    return x
+
+
+def axpby(prec, alpha: float, y, beta: float, z) -> np.ndarray:
+    """x = RN(alpha*y + RN(beta*z)) elementwise; alpha, beta are effective factors."""
+    y, z = _arr(y), _arr(z)
+    assert y.size == z.size
+    x = np.empty_like(y)
+    _load().o_axpby(prec_code(prec), y.size, float(alpha), _ptr(y), float(beta), _ptr(z), _ptr(x))
+    return x
+
+
+def dot(x, y) -> float:
+    x, y = _arr(x), _arr(y)
+    assert x.size == y.size
+    return _load().o_dot(x.size, _ptr(x), 1, _ptr(y), 1)
+
+
+def nrm2(x) -> float:
+    x = _arr(x)
+    return _load().o_nrm2(x.size, _ptr(x))
+
+
+def gemv(A, x, layout: int = ROW_MAJOR, trans: int = 0, m: int | None = None,
+         n: int | None = None, lda: int | None = None) -> np.ndarray:
+    """y = op(A) x.  ``A`` is either a 2-D array (m x n in its natural index
+    order; its layout argument then says how it is laid out in memory) or a
+    flat buffer with explicit m, n, lda."""
+    A = np.asarray(A)
+    if A.ndim == 2:
+        m, n = A.shape
+        flat = _arr(A.reshape(-1) if layout == ROW_MAJOR else A.T.reshape(-1))
+        lda = n if layout == ROW_MAJOR else m
+    else:
+        flat = _arr(A)
+        assert m is not None and n is not None and lda is not None
+    x = _arr(x)
+    out_len = n if trans else m
+    assert x.size == (m if trans else n)
+    y = np.empty(out_len, dtype=np.float64)
+    if out_len:
+        _load().o_gemv(layout, int(trans), m, n, _ptr(flat), lda, _ptr(x), _ptr(y))
+    return y
+
+
+def ger(prec, u, v, layout: int = ROW_MAJOR, lda: int | None = None) -> np.ndarray:
+    """A = u v^T with each entry rounded once to ``prec``.  Returns the flat
+    buffer in ``layout`` order with leading dimension ``lda``."""
+    u, v = _arr(u), _arr(v)
+    m, n = u.size, v.size
+    if lda is None:
+        lda = n if layout == ROW_MAJOR else m
+    lines = m if layout == ROW_MAJOR else n
+    A = np.zeros(lines * lda, dtype=np.float64)
+    _load().o_ger(prec_code(prec), layout, m, n, _ptr(u), _ptr(v), _ptr(A), lda)
+    return A
+
+
+def dot_backward(prec, zbar: float, x, y):
+    """Gradient of z = <x, y>: dx_i = RN(zbar*y_i), dy_i = RN(zbar*x_i)."""
+    # Written as a scaled addition with beta = 0 and z = the scaled operand,
+    # the same call sequence the library's adjoint uses.
+    return (axpby(prec, zbar, y, 0.0, y), axpby(prec, zbar, x, 0.0, x))
+
+
+def gemv_backward(prec, A, x, ybar, layout: int = ROW_MAJOR):
+    """Gradients of y = A x: dx = A^T ybar (reduction) and dA = ybar x^T."""
+    dx = gemv(A, ybar, layout=layout, trans=1)
+    dA = ger(prec, ybar, x, layout=layout)
+    return dx, dA
