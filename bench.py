@@ -1,0 +1,225 @@
+"""Benchmark of the bandwidth-limited BLAS-1/2 kernels on one MI355X.
+
+One step is one pass over the paper-scale plain workload: for float32 and
+float64 storage, the scaled vector addition x = a y + b z, the inner product and
+the norm at n = 1e5, 1e6, 1e7 and 2^26, and the matrix-vector product y = A x
+with A 4096 x 4096 and 16384 x 16384 in row- and column-major layout.  Inputs
+are seeded synthetic data (uniform on [-1, 1)) resident in HBM before timing.
+
+``value`` is the whole step's algorithmic bytes (minimal bytes: 3ns for the
+addition, 2ns for the inner product, ns for the norm, (mn + m + n) elements for
+the matrix-vector product) divided by the measured step time, in GB/s.
+The JSON line also carries, for the dominant kernel (16384 x 16384 float64
+row-major GEMV), its roofline against the 8 TB/s HBM peak measured with HIP
+events around each of its launches in the timed region, and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+DOMINANT = ("gemv", "f64", "row", 16384)
+DOMINANT_KERNEL = "k_gemv_rows<double, 2, 4, false>"
+DOMINANT_SOURCE = os.path.join(HERE, "paper_1409_0669_amd", "csrc", "gemv.hip")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "gemv_rows_f64_16384_traffic.txt")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="time budget of the CPU oracle sample")
+    ap.add_argument("--tuning", default=None, help="tuning table to load before timing")
+    ap.add_argument("--breakdown", action="store_true", help="print per-operation rates to stderr")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(torch, W, ops):
+    """Device inputs of one step and the list of (name, bytes, callable)."""
+    sizes = W.PAPER_SCALE["vector_sizes"]
+    work = []
+    keep = []
+    dev = "cuda"
+    for dt in ("f32", "f64"):
+        tdt = {"f32": torch.float32, "f64": torch.float64}[dt]
+        s = 4 if dt == "f32" else 8
+        for i, n in enumerate(sizes):
+            y = W.device_draw(n, dt, 0, 100 + i)
+            z = W.device_draw(n, dt, 0, 200 + i)
+            x = torch.empty_like(y)
+            out_d = torch.empty((), dtype=tdt, device=dev)
+            out_n = torch.empty((), dtype=tdt, device=dev)
+            keep += [y, z, x, out_d, out_n]
+            work.append((("axpby", dt, n), 3 * n * s,
+                         lambda y=y, z=z, x=x: ops.axpby(0.75, y, -1.25, z, out=x)))
+            work.append((("dot", dt, n), 2 * n * s, lambda y=y, z=z, o=out_d: ops.dot(y, z, out=o)))
+            work.append((("nrm2", dt, n), n * s, lambda y=y, o=out_n: ops.nrm2(y, out=o)))
+        for j, m in enumerate(W.PAPER_SCALE["gemv_shapes"]):
+            m, n = m
+            A_row = W.device_draw(m * n, dt, 0, 300 + j).reshape(m, n)
+            A_col = A_row.t().contiguous().t()  # same matrix, column-major storage
+            xv = W.device_draw(n, dt, 0, 400 + j)
+            yv_r = torch.empty(m, dtype=tdt, device=dev)
+            yv_c = torch.empty(m, dtype=tdt, device=dev)
+            keep += [A_row, A_col, xv, yv_r, yv_c]
+            nbytes = (m * n + m + n) * s
+            work.append((("gemv", dt, "row", m), nbytes, lambda A=A_row, x=xv, y=yv_r: ops.gemv(A, x, out=y)))
+            work.append((("gemv", dt, "col", m), nbytes, lambda A=A_col, x=xv, y=yv_c: ops.gemv(A, x, out=y)))
+    return work, keep
+
+
+def cpu_baseline(W, oracle, seconds):
+    """The oracle (plain single-threaded C) on a bounded sample of the same
+    workload: the vector operations at n = 1e5, 1e6, 1e7 and the 4096 x 4096
+    matrix-vector products in both layouts, float32 and float64 values,
+    repeated until the time budget is used."""
+    import numpy as np
+    items = []
+    for dt in ("f32", "f64"):
+        s = 4 if dt == "f32" else 8
+        for i, n in enumerate((10 ** 5, 10 ** 6, 10 ** 7)):
+            y = W.widen(W.quantize(W.uniform(n, 0, 100 + i), dt), dt)
+            z = W.widen(W.quantize(W.uniform(n, 0, 200 + i), dt), dt)
+            a, b = oracle.scalar(dt, 0.75), oracle.scalar(dt, -1.25)
+            items.append((3 * n * s, lambda y=y, z=z, a=a, b=b, dt=dt: oracle.axpby(dt, a, y, b, z)))
+            items.append((2 * n * s, lambda y=y, z=z: oracle.dot(y, z)))
+            items.append((n * s, lambda y=y: oracle.nrm2(y)))
+        m = n = 4096
+        A = W.widen(W.quantize(W.uniform(m * n, 0, 300), dt), dt).reshape(m, n)
+        xv = W.widen(W.quantize(W.uniform(n, 0, 400), dt), dt)
+        At = np.ascontiguousarray(A.T).reshape(-1)
+        nb = (m * n + m + n) * s
+        items.append((nb, lambda A=A, x=xv: oracle.gemv(A, x)))
+        items.append((nb, lambda F=At, x=xv: oracle.gemv(F, x, layout=oracle.COL_MAJOR, m=m, n=n, lda=m)))
+    done_bytes, passes = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        for nb, fn in items:
+            fn()
+            done_bytes += nb
+        passes += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt_s = time.perf_counter() - t0
+    return {"value": round(done_bytes / dt_s / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle (single-threaded C, fp64 Dot2 reductions) on axpby/dot/nrm2 at n=1e5,1e6,1e7 "
+                      "and GEMV 4096x4096 row- and column-major, f32 and f64 values; %d passes in %.1f s"
+                      % (passes, dt_s)}
+
+
+def traffic_for_dominant():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src_hash = hashlib.sha256(open(DOMINANT_SOURCE, "rb").read()).hexdigest()
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != src_hash:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_1409_0669_amd import ops
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(2)
+    if args.tuning:
+        ops.load_tuning(args.tuning)
+    t0 = time.perf_counter()
+    work, keep = build_workload(torch, W, ops)
+    torch.cuda.synchronize()
+    log("inputs ready in %.1f s (%d operations per step)" % (time.perf_counter() - t0, len(work)))
+
+    step_bytes = sum(b for _, b, _ in work)
+    for _ in range(args.warmup):
+        for _, _, fn in work:
+            fn()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    events = {name: [] for name, _, _ in work}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        for name, _, fn in work:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            events[name].append((e0, e1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = step_bytes * args.steps / elapsed / 1e9
+
+    per_op = {}
+    for name, nbytes, _ in work:
+        ms = sum(a.elapsed_time(b) for a, b in events[name]) / len(events[name])
+        per_op[name] = (nbytes, ms)
+    dom_bytes, dom_ms = per_op[DOMINANT]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for_dominant(),
+                "kernel": DOMINANT_KERNEL, "avg_launch_us": round(dom_ms * 1e3, 2),
+                "algorithmic_bytes": dom_bytes}
+    breakdown = {"%s %s %s" % (k[0], k[1], "x".join(map(str, k[2:]))): round(b / (ms * 1e-3) / 1e9, 1)
+                 for k, (b, ms) in per_op.items()}
+    if args.breakdown:
+        for k, v in breakdown.items():
+            log("%-28s %9.1f GB/s" % (k, v))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the CPU oracle sample (~%.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(W, oracle, args.cpu_seconds)
+
+    line = {
+        "metric": "achieved HBM GB/s (and % of peak) for axpy, dot, GEMV fwd/adjoint, plain vs batched/BF16",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "paper-scale plain kernels: axpby, dot, nrm2 at n=1e5,1e6,1e7,2^26 and GEMV "
+                               "4096^2, 16384^2 row- and column-major; f32 and f64; uniform[-1,1) seed 0",
+                   "bytes_per_step": step_bytes, "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
+        "roofline": roofline, "cpu_baseline": cpu, "breakdown_gbs": breakdown,
+    }
+    print(json.dumps(line), flush=True)
+    del keep
+
+
+if __name__ == "__main__":
+    main()

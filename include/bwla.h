@@ -1,0 +1,239 @@
+/*
+ * bwla.h -- C ABI of the bandwidth-limited linear algebra library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operations are those whose performance portability is studied in
+ * Rupp, Tillet, Rudolf, Weinbub, Grasser, Juengel, "Performance Portability
+ * Study of Linear Algebra Kernels in OpenCL", IWOCL 2014 (arXiv:1409.0669),
+ * Section 2: vector copy x <- y, scaled vector addition x <- alpha y + beta z,
+ * the inner product <x, y>, and the dense matrix-vector product; plus the
+ * Euclidean norm, the transposed product and the rank-1 overwrite needed for
+ * gradients, a batched launch for many uneven problems, and a fused
+ * conjugate-gradient-style update.
+ *
+ * Conventions shared by every entry point
+ *  - All data pointers are DEVICE pointers owned by the caller.  The library
+ *    never frees them and keeps no reference after the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is only enqueued; no call synchronises the host with the device.
+ *  - Sizes and leading dimensions are int64_t element counts.
+ *  - Arguments are validated before anything is enqueued; on any error code
+ *    nothing was enqueued, and bwla_last_error() holds a message for the
+ *    calling thread.  Device faults surface at the caller's next
+ *    synchronisation, as with any HIP kernel.
+ *  - Storage types: BWLA_F64 (double), BWLA_F32 (float), BWLA_BF16 (bfloat16).
+ *    Arithmetic is carried out in the "compute precision": double for f64
+ *    storage, float for f32 and bf16 storage.  Every conversion to a narrower
+ *    format rounds to nearest, ties to even.
+ *  - Reductions (dot, nrm2, gemv) take a workspace `ws` of at least
+ *    bwla_workspace_size() bytes.  The workspace must be zero-filled once
+ *    when it is allocated; every call leaves its first BWLA_WS_COUNTER_BYTES
+ *    bytes zero again when it completes, so one workspace can serve any
+ *    sequence of calls on ONE stream.  Calls that may run concurrently (other
+ *    streams) need separate workspaces.  No entry point allocates device
+ *    memory except bwla_batch_plan_create.
+ */
+#ifndef BWLA_H
+#define BWLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BWLA_ABI_VERSION 1
+#define BWLA_WS_COUNTER_BYTES 65536
+
+typedef enum {
+    BWLA_OK = 0,
+    BWLA_ERR_INVALID_ARG = 1,   /* negative size, NULL pointer, bad lda, overlap */
+    BWLA_ERR_UNSUPPORTED = 2,   /* dtype / accumulation / output-type combination */
+    BWLA_ERR_WORKSPACE = 3,     /* ws missing or smaller than bwla_workspace_size() */
+    BWLA_ERR_HIP = 4,           /* a HIP runtime call or kernel launch failed */
+    BWLA_ERR_NOT_CAPTURABLE = 5 /* the call would allocate while the stream is capturing */
+} bwla_status;
+
+typedef enum { BWLA_F64 = 0, BWLA_F32 = 1, BWLA_BF16 = 2 } bwla_dtype;
+typedef enum { BWLA_ROW_MAJOR = 0, BWLA_COL_MAJOR = 1 } bwla_layout;
+
+/* Accumulation of reductions.  PLAIN: one running sum per thread in the
+ * compute precision.  COMPENSATED: the running sum carries its rounding error
+ * (TwoSum) and, for f64/f32, the product error (TwoProduct by fma) -- the
+ * Dot2 scheme of Ogita, Rump and Oishi; for bf16 the products are exact in
+ * f32 and only the sum is compensated (Kahan-style).  In both modes, partial
+ * sums leave the thread as float64 and every combine across threads and
+ * work-groups is done in float64 (double-float64 pairs when COMPENSATED). */
+typedef enum { BWLA_ACC_PLAIN = 0, BWLA_ACC_COMPENSATED = 1 } bwla_acc;
+
+/* Loop increment of the streaming kernels, the paper's two kernel skeletons
+ * (Section 2): GLOBAL advances each thread by the whole grid; LOCAL gives each
+ * work-group one contiguous chunk, advanced by the work-group size. */
+typedef enum { BWLA_INC_GLOBAL = 0, BWLA_INC_LOCAL = 1 } bwla_increment;
+
+typedef enum {
+    BWLA_OP_COPY = 0,
+    BWLA_OP_AXPBY = 1,
+    BWLA_OP_DOT = 2,       /* also used by nrm2 */
+    BWLA_OP_GEMV_ROWS = 3, /* each output is a reduction along a contiguous line of A */
+    BWLA_OP_GEMV_COLS = 4, /* each output runs along a contiguous line; reduction across lines */
+    BWLA_OP_GER = 5,
+    BWLA_OP_COUNT = 6
+} bwla_op;
+
+/* Kernel configuration: the paper's triple (kernel source, local work size,
+ * global work size; Section 1 and Section 2) with the source variant spelled
+ * out.  A zero field means "library default".  Which fields an op uses:
+ *   COPY, AXPBY, DOT: block, vec, unroll, grid, increment
+ *   GEMV_ROWS:        block, vec, rows (lines per block), split (blocks along a line)
+ *   GEMV_COLS:        block, vec, unroll (lines in flight), split (blocks across lines)
+ *   GER:              block, vec, rows
+ * block:  threads per work-group, a multiple of 64 in [64, 1024]
+ * vec:    consecutive elements per thread per access: 1, 2, 4, 8 or 16 (the
+ *         paper's vector data types); widths above 16 bytes are issued as
+ *         several 16-byte loads
+ * unroll: independent accesses in flight per thread per iteration: 1, 2 or 4
+ * grid:   number of work-groups (streaming and reductions)
+ * rows:   1, 2, 4 or 8
+ * split:  >= 1; values above 1 make several work-groups share one output
+ *         tile, combining their float64 partials in a fixed order. */
+typedef struct {
+    int32_t block, vec, unroll, grid, increment, rows, split;
+} bwla_config;
+
+/* ---- vector copy: x <- y (paper Section 2, first kernel) ----------------
+ * n >= 0 elements of type t.  x may equal y (no-op); partial overlap is an
+ * error.  Nothing is enqueued for n == 0. */
+bwla_status bwla_copy(bwla_dtype t, int64_t n, const void *y, void *x, void *stream);
+
+/* ---- scaled vector addition: x <- alpha y + beta z (paper Section 2) ------
+ * Effective factors (compute precision c): a = RN_c(alpha) if alpha_dev is
+ * NULL, else RN_c(RN_c(alpha) * (*alpha_dev)); likewise b.  alpha_dev and
+ * beta_dev, when given, point to ONE device element of the compute type
+ * (double for f64 storage, float otherwise).  Each element is computed as
+ *     x_i = RN_t( fma_c(a, y_i, RN_c(b * z_i)) )
+ * so the result is bitwise reproducible.  z is read even when b == 0 (IEEE
+ * semantics).  x may equal y or z exactly (in-place updates); partial overlap
+ * is an error. */
+bwla_status bwla_axpby(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev,
+                       const void *y, double beta, const void *beta_dev, const void *z,
+                       void *x, void *stream);
+
+/* ---- inner product: out <- <x, y> (paper Section 2, inner product) --------
+ * Two-stage reduction: each work-group writes a float64 partial, and the
+ * last work-group to finish (atomic ticket) combines all partials in a fixed
+ * order, so the result is deterministic for a given configuration.  out is
+ * ONE device element of out_t: BWLA_F64 for f64 input; BWLA_F32 or BWLA_F64
+ * for f32/bf16 input.  n == 0 writes 0. */
+bwla_status bwla_dot(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
+                     bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Euclidean norm: out <- sqrt(<x, x>) (no overflow scaling) -------------
+ * Same reduction as bwla_dot on (x, x), reading x once. */
+bwla_status bwla_nrm2(bwla_dtype t, bwla_acc acc, int64_t n, const void *x,
+                      bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- dense matrix-vector product: y <- op(A) x (paper Section 2) ----------
+ * A is m x n.  Row-major: A_ij at A[i*lda + j], lda >= max(1, n).
+ * Column-major: A_ij at A[i + j*lda], lda >= max(1, m).
+ * trans == 0: op(A) = A, x has n entries, y has m.  trans == 1: op(A) = A^T,
+ * x has m entries, y has n.  y is overwritten (never read) in out_t (F64 for
+ * f64 storage; F32 or F64 otherwise).  A zero-length reduction writes y = 0.
+ * y must not overlap A or x. */
+bwla_status bwla_gemv(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m,
+                      int64_t n, const void *A, int64_t lda, const void *x, bwla_dtype out_t,
+                      void *y, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- rank-1 overwrite: A <- u v^T ------------------------------------------
+ * The gradient of y = A x with respect to A for an incoming gradient u = ybar
+ * and v = x.  A is m x n in the given layout and leading dimension; every
+ * entry is RN_t(u_i * v_j) computed in the compute precision, so the result
+ * is bitwise reproducible.  Entries between the row (column) length and lda
+ * are not touched.  A must not overlap u or v. */
+bwla_status bwla_ger(bwla_dtype t, bwla_layout layout, int64_t m, int64_t n, const void *u,
+                     const void *v, void *A, int64_t lda, void *stream);
+
+/* ---- fused update of a conjugate-gradient-style step ----------------------
+ * In one pass over the vectors: x <- x + a p, r <- r - a q, out <- <r, r>,
+ * with a = RN_c(alpha) (or RN_c(RN_c(alpha) * (*alpha_dev))).  Elementwise
+ * results are bitwise those of bwla_axpby(x; alpha=a, y=p, beta=1, z=x) and
+ * bwla_axpby(r; alpha=-a, y=q, beta=1, z=r); the reduction uses the new r.
+ * Workspace as for bwla_dot. */
+bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha,
+                           const void *alpha_dev, void *x, const void *p, void *r,
+                           const void *q, bwla_dtype out_t, void *out, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* Bytes of workspace that the call with these arguments needs under the
+ * current configuration table.  `op` is the public operation: BWLA_OP_DOT for
+ * dot/nrm2/cg_update (m ignored, n = length), BWLA_OP_GEMV_ROWS or
+ * BWLA_OP_GEMV_COLS are both accepted for bwla_gemv (the kernel is chosen
+ * from layout and trans). */
+bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_layout layout,
+                                int trans, int64_t m, int64_t n, size_t *bytes);
+
+/* ---- batched uneven problems in one persistent launch -------------------
+ * A plan holds many row-major GEMVs (y = A x, out_t output) and many dots
+ * (out = <x, y>, out_t output) of one storage type.  Work is flattened into
+ * items (row tiles of a GEMV, chunks of a dot) ordered largest first; a
+ * persistent grid takes items from an atomic counter.  Each dot's chunk
+ * partials are combined in chunk order by the last chunk to finish, so
+ * results do not depend on the batch order or on scheduling.
+ * create: copies the descriptors to the device and allocates the plan's own
+ *         counters and partial slots (the only allocating call; not allowed
+ *         while `stream` capture is active).
+ * run:    enqueues the counter reset and the persistent kernel.
+ * capture: records the same two kernels into a HIP graph owned by the plan.
+ * replay: launches the captured graph.
+ * Descriptor pointers must stay valid while the plan is used. */
+typedef struct bwla_batch_plan bwla_batch_plan;
+typedef struct {
+    const void *A;
+    int64_t m, n, lda;
+    const void *x;
+    void *y;
+} bwla_gemv_desc;
+typedef struct {
+    const void *x;
+    const void *y;
+    int64_t n;
+    void *out;
+} bwla_dot_desc;
+
+bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
+                                   const bwla_gemv_desc *g, int32_t ng, const bwla_dot_desc *d,
+                                   int32_t nd, const bwla_config *cfg, bwla_batch_plan **out);
+bwla_status bwla_batch_run(bwla_batch_plan *p, void *stream);
+bwla_status bwla_batch_capture(bwla_batch_plan *p, void *stream);
+bwla_status bwla_batch_replay(bwla_batch_plan *p, void *stream);
+/* Number of work items, persistent grid size and algorithmic bytes moved. */
+bwla_status bwla_batch_info(const bwla_batch_plan *p, int64_t *items, int32_t *grid,
+                            double *bytes);
+void bwla_batch_plan_destroy(bwla_batch_plan *p);
+
+/* ---- configuration table ---------------------------------------------------
+ * One entry per (op, storage type, size class).  Size class by the bytes the
+ * call streams: 0 < 1 MiB, 1 < 16 MiB, 2 < 256 MiB, 3 otherwise; pass -1 to
+ * set every class.  cfg == NULL restores the defaults.  The table is shared
+ * by all threads (mutex-guarded). */
+bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int size_class, const bwla_config *cfg);
+/* The configuration a call with this op, type and shape would use after
+ * defaults are resolved (m = lines, n = line length for GEMV/GER; m ignored
+ * for vectors). */
+bwla_status bwla_get_config(bwla_op op, bwla_dtype t, int64_t m, int64_t n, bwla_config *cfg);
+/* Load a tuning table written by the autotuner: text, one entry per line,
+ * "op dtype size_class block vec unroll grid increment rows split", '#'
+ * starts a comment. */
+bwla_status bwla_load_tuning(const char *path);
+
+const char *bwla_status_string(bwla_status st);
+const char *bwla_last_error(void); /* message of the last failed call on this thread */
+int bwla_abi_version(void);
+/* Number of compute units of the current device (used for default grids). */
+int bwla_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BWLA_H */

@@ -1,0 +1,964 @@
+// api.cpp -- the C ABI declared in include/bwla.h: argument validation,
+// configuration table and defaults, workspace sizing, kernel dispatch and
+// batch plans.  Every check runs before anything is enqueued.
+#include "bwla.h"
+#include "device.hpp"
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace bwla;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bwla_status fail(bwla_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+bwla_status hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return BWLA_OK;
+    return fail(BWLA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_dtype(int t) { return t == BWLA_F64 || t == BWLA_F32 || t == BWLA_BF16; }
+size_t dsize(int t) { return t == BWLA_F64 ? 8 : (t == BWLA_F32 ? 4 : 2); }
+int native_vec(int t) { return (int)(16 / dsize(t)); }
+
+// ---------------------------------------------------------------------------
+// device properties
+// ---------------------------------------------------------------------------
+int device_cus()
+{
+    static std::mutex mu;
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cached[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+// ---------------------------------------------------------------------------
+// configuration table
+// ---------------------------------------------------------------------------
+constexpr int kClasses = 4;
+std::mutex g_cfg_mu;
+bwla_config g_table[BWLA_OP_COUNT][3][kClasses]; // zero-initialised: all defaults
+
+int size_class(double bytes)
+{
+    if (bytes < 1048576.0)
+        return 0;
+    if (bytes < 16777216.0)
+        return 1;
+    if (bytes < 268435456.0)
+        return 2;
+    return 3;
+}
+
+bwla_config lookup(int op, int t, double bytes)
+{
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    return g_table[op][t][size_class(bytes)];
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Largest pack width (elements, power of two, <= want) such that every address
+// in `ptrs` and every line stride `ld` keeps packs aligned.
+int fit_vec(int want, size_t esize, std::initializer_list<const void *> ptrs, int64_t ld = 0)
+{
+    int v = want;
+    while (v > 1) {
+        bool ok = true;
+        for (const void *p : ptrs)
+            if (p && ((uintptr_t)p % (v * esize)) != 0)
+                ok = false;
+        if (ld && (ld % v) != 0)
+            ok = false;
+        if (ok)
+            break;
+        v >>= 1;
+    }
+    return v;
+}
+
+bwla_status check_cfg(const bwla_config &c)
+{
+    if (c.block && (c.block < 64 || c.block > 1024 || c.block % 64))
+        return fail(BWLA_ERR_INVALID_ARG, "config: block %d is not a multiple of 64 in [64, 1024]", c.block);
+    if (c.vec && !(is_pow2(c.vec) && c.vec <= 16))
+        return fail(BWLA_ERR_INVALID_ARG, "config: vec %d not in {1,2,4,8,16}", c.vec);
+    if (c.unroll && !(c.unroll == 1 || c.unroll == 2 || c.unroll == 4))
+        return fail(BWLA_ERR_INVALID_ARG, "config: unroll %d not in {1,2,4}", c.unroll);
+    if (c.rows && !(is_pow2(c.rows) && c.rows <= 8))
+        return fail(BWLA_ERR_INVALID_ARG, "config: rows %d not in {1,2,4,8}", c.rows);
+    if (c.grid < 0 || c.split < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "config: negative grid or split");
+    if (c.increment != BWLA_INC_GLOBAL && c.increment != BWLA_INC_LOCAL)
+        return fail(BWLA_ERR_INVALID_ARG, "config: increment %d", c.increment);
+    return BWLA_OK;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// --- resolved configurations ---------------------------------------------
+// Streaming and reduction kernels over n elements.
+Cfg resolve_vector(int op, int t, int64_t n, std::initializer_list<const void *> ptrs, int nstreams)
+{
+    bwla_config u = lookup(op, t, (double)n * dsize(t) * nstreams);
+    Cfg c;
+    c.block = u.block ? u.block : 256;
+    c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), ptrs);
+    c.unroll = u.unroll ? u.unroll : 4;
+    c.inc = u.increment;
+    c.rows = 1;
+    c.split = 1;
+    const int64_t npack = std::max<int64_t>(1, n / c.vec);
+    const int64_t one_pass = std::max<int64_t>(1, ceil_div(npack, (int64_t)c.block * c.unroll));
+    int64_t grid = u.grid;
+    if (!grid) {
+        if (op == BWLA_OP_DOT)
+            grid = std::min<int64_t>(one_pass, (int64_t)device_cus() * 8);
+        else
+            grid = one_pass;
+    }
+    grid = std::min<int64_t>(grid, 1 << 30);
+    if (op == BWLA_OP_DOT) // partial slots and the final combine stay small
+        grid = std::min<int64_t>(grid, 65536);
+    c.grid = (int)std::max<int64_t>(grid, 1);
+    return c;
+}
+
+Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const void *v)
+{
+    bwla_config u = lookup(BWLA_OP_GEMV_ROWS, t, (double)L * K * dsize(t));
+    Cfg c;
+    c.block = u.block ? u.block : 256;
+    c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A, v}, ld);
+    c.unroll = 1;
+    c.grid = 0;
+    c.inc = 0;
+    c.rows = u.rows ? u.rows : 4;
+    const int64_t groups = ceil_div(L, c.rows);
+    int64_t split = u.split;
+    if (!split) {
+        const int64_t target = (int64_t)device_cus() * 8;
+        const int64_t kpack = std::max<int64_t>(1, K / c.vec);
+        split = groups >= target / 2 ? 1 : ceil_div(target, groups);
+        split = std::min<int64_t>(split, std::max<int64_t>(1, kpack / (2 * c.block)));
+    }
+    if (groups > kMaxCounters)
+        split = 1;
+    split = std::max<int64_t>(1, std::min<int64_t>(split, std::max<int64_t>(1, K)));
+    split = std::min<int64_t>(split, (int64_t)(0x7fffffff / std::max<int64_t>(1, groups)));
+    c.split = (int)split;
+    return c;
+}
+
+Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const void *v)
+{
+    bwla_config u = lookup(BWLA_OP_GEMV_COLS, t, (double)L * K * dsize(t));
+    Cfg c;
+    c.block = u.block ? u.block : 256;
+    c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A}, ld);
+    c.unroll = u.unroll ? u.unroll : 4;
+    c.grid = 0;
+    c.inc = 0;
+    c.rows = 1;
+    const int64_t tiles = ceil_div(K, 64 * (int64_t)c.vec);
+    int64_t split = u.split;
+    if (!split) {
+        const int64_t target = (int64_t)device_cus() * 8;
+        const int64_t waves = c.block / 64;
+        split = tiles >= target ? 1 : ceil_div(target, tiles);
+        split = std::min<int64_t>(split, std::max<int64_t>(1, L / (waves * 16)));
+    }
+    if (tiles > kMaxCounters)
+        split = 1;
+    split = std::max<int64_t>(1, std::min<int64_t>(split, std::max<int64_t>(1, L)));
+    split = std::min<int64_t>(split, (int64_t)(0x7fffffff / std::max<int64_t>(1, tiles)));
+    c.split = (int)split;
+    return c;
+}
+
+Cfg resolve_ger(int t, int64_t L, int64_t K, const void *a, const void *b, const void *A, int64_t ld)
+{
+    bwla_config u = lookup(BWLA_OP_GER, t, (double)L * K * dsize(t));
+    Cfg c;
+    c.block = u.block ? u.block : 256;
+    c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {b, A}, ld);
+    c.unroll = 1;
+    c.grid = 0;
+    c.inc = 0;
+    c.rows = u.rows ? u.rows : 4;
+    c.split = 1;
+    (void)a;
+    return c;
+}
+
+size_t ws_dot(const Cfg &c) { return kCounterBytes + (size_t)c.grid * sizeof(DD); }
+size_t ws_rows(const Cfg &c, int64_t L)
+{
+    if (c.split <= 1)
+        return 0;
+    return kCounterBytes + (size_t)ceil_div(L, c.rows) * c.split * c.rows * sizeof(DD);
+}
+size_t ws_cols(const Cfg &c, int64_t K)
+{
+    if (c.split <= 1)
+        return 0;
+    return kCounterBytes + (size_t)ceil_div(K, 64 * (int64_t)c.vec) * c.split * 64 * c.vec * sizeof(DD);
+}
+
+// --- overlap checks ----------------------------------------------------------
+struct Span {
+    uintptr_t lo, hi; // [lo, hi)
+};
+Span span(const void *p, size_t bytes) { return Span{(uintptr_t)p, (uintptr_t)p + bytes}; }
+bool overlaps(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi && a.hi > a.lo && b.hi > b.lo; }
+bool same(Span a, Span b) { return a.lo == b.lo && a.hi == b.hi; }
+size_t matrix_bytes(int64_t lines, int64_t K, int64_t ld, size_t es)
+{
+    if (lines <= 0 || K <= 0)
+        return 0;
+    return (size_t)((lines - 1) * ld + K) * es;
+}
+
+bwla_status out_type_ok(int t, int out_t)
+{
+    if (!valid_dtype(out_t) || out_t == BWLA_BF16)
+        return fail(BWLA_ERR_UNSUPPORTED, "output type %d: results are float64 or float32", out_t);
+    if (t == BWLA_F64 && out_t != BWLA_F64)
+        return fail(BWLA_ERR_UNSUPPORTED, "f64 input requires an f64 output");
+    return BWLA_OK;
+}
+
+template <typename F> hipError_t by_type(int t, F &&f)
+{
+    switch (t) {
+    case BWLA_F64: return f((double *)nullptr);
+    case BWLA_F32: return f((float *)nullptr);
+    default: return f((bf16_t *)nullptr);
+    }
+}
+
+// Common front half of dot/nrm2/cg: validation of the reduction arguments.
+bwla_status check_reduction(int t, int acc, int64_t n, int out_t, void *out, void *ws, size_t ws_bytes,
+                            size_t need)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (acc != BWLA_ACC_PLAIN && acc != BWLA_ACC_COMPENSATED)
+        return fail(BWLA_ERR_UNSUPPORTED, "accumulation mode %d", acc);
+    if (n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    bwla_status st = out_type_ok(t, out_t);
+    if (st)
+        return st;
+    if (!out)
+        return fail(BWLA_ERR_INVALID_ARG, "out is NULL");
+    if (need && (!ws || ws_bytes < need))
+        return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given%s", need, ws_bytes,
+                    ws ? "" : " (NULL)");
+    return BWLA_OK;
+}
+
+} // namespace
+
+// ===========================================================================
+// entry points
+// ===========================================================================
+extern "C" {
+
+int bwla_abi_version(void) { return BWLA_ABI_VERSION; }
+int bwla_device_cus(void) { return device_cus(); }
+const char *bwla_last_error(void) { return g_last_error.c_str(); }
+
+const char *bwla_status_string(bwla_status st)
+{
+    switch (st) {
+    case BWLA_OK: return "ok";
+    case BWLA_ERR_INVALID_ARG: return "invalid argument";
+    case BWLA_ERR_UNSUPPORTED: return "unsupported";
+    case BWLA_ERR_WORKSPACE: return "workspace too small";
+    case BWLA_ERR_HIP: return "HIP error";
+    case BWLA_ERR_NOT_CAPTURABLE: return "not capturable";
+    }
+    return "unknown status";
+}
+
+bwla_status bwla_copy(bwla_dtype t, int64_t n, const void *y, void *x, void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    if (n == 0)
+        return BWLA_OK;
+    if (!x || !y)
+        return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
+    Span sx = span(x, n * dsize(t)), sy = span(y, n * dsize(t));
+    if (same(sx, sy))
+        return BWLA_OK;
+    if (overlaps(sx, sy))
+        return fail(BWLA_ERR_INVALID_ARG, "x partially overlaps y");
+    Cfg c = resolve_vector(BWLA_OP_COPY, t, n, {x, y}, 2);
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_copy<T>(n, y, x, c, (hipStream_t)stream);
+    });
+    return hip_check(e, "copy launch");
+}
+
+bwla_status bwla_axpby(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev, const void *y,
+                       double beta, const void *beta_dev, const void *z, void *x, void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    if (n == 0)
+        return BWLA_OK;
+    if (!x || !y || !z)
+        return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
+    const size_t b = n * dsize(t);
+    Span sx = span(x, b), sy = span(y, b), sz = span(z, b);
+    if ((overlaps(sx, sy) && !same(sx, sy)) || (overlaps(sx, sz) && !same(sx, sz)))
+        return fail(BWLA_ERR_INVALID_ARG, "x partially overlaps y or z (only exact aliasing is allowed)");
+    const size_t cs = t == BWLA_F64 ? 8 : 4;
+    Span sxa = span(x, b);
+    if ((alpha_dev && overlaps(sxa, span(alpha_dev, cs))) || (beta_dev && overlaps(sxa, span(beta_dev, cs))))
+        return fail(BWLA_ERR_INVALID_ARG, "a device scalar lies inside the output x");
+    Cfg c = resolve_vector(BWLA_OP_AXPBY, t, n, {x, y, z}, 3);
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_axpby<T>(n, alpha, alpha_dev, y, beta, beta_dev, z, x, c, (hipStream_t)stream);
+    });
+    return hip_check(e, "axpby launch");
+}
+
+static bwla_status dot_common(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
+                              bool square, bwla_dtype out_t, void *out, void *ws, size_t ws_bytes,
+                              void *stream)
+{
+    Cfg c = resolve_vector(BWLA_OP_DOT, t, n, {x, y}, square ? 1 : 2);
+    const size_t need = n > 0 && c.grid > 1 ? ws_dot(c) : 0;
+    bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
+    if (st)
+        return st;
+    if (n > 0 && (!x || (!square && !y)))
+        return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
+    const size_t os = out_t == BWLA_F64 ? 8 : 4;
+    Span so = span(out, os);
+    if (n > 0 && (overlaps(so, span(x, n * dsize(t))) || (!square && overlaps(so, span(y, n * dsize(t))))))
+        return fail(BWLA_ERR_INVALID_ARG, "out overlaps an input");
+    if (n == 0)
+        return hip_check(launch_fill_zero(out, 1, out_t == BWLA_F64, (hipStream_t)stream), "fill launch");
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_dot<T>(n, acc == BWLA_ACC_COMPENSATED, square, x, square ? x : y,
+                             out_t == BWLA_F64, out, ws, c, (hipStream_t)stream);
+    });
+    return hip_check(e, square ? "nrm2 launch" : "dot launch");
+}
+
+bwla_status bwla_dot(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
+                     bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream)
+{
+    return dot_common(t, acc, n, x, y, false, out_t, out, ws, ws_bytes, stream);
+}
+
+bwla_status bwla_nrm2(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, bwla_dtype out_t,
+                      void *out, void *ws, size_t ws_bytes, void *stream)
+{
+    return dot_common(t, acc, n, x, nullptr, true, out_t, out, ws, ws_bytes, stream);
+}
+
+// Which kernel serves (layout, trans), and the line view of A.
+struct GemvPlan {
+    bool rows;       // rows kernel (reduction along lines) or cols kernel
+    int64_t L, K;    // lines, elements per line
+    int64_t out_len; // entries of y
+    int64_t in_len;  // entries of x
+};
+
+static GemvPlan gemv_plan(int layout, int trans, int64_t m, int64_t n)
+{
+    GemvPlan g;
+    const bool row_major = layout == BWLA_ROW_MAJOR;
+    g.L = row_major ? m : n;
+    g.K = row_major ? n : m;
+    g.rows = row_major ? !trans : trans;
+    g.out_len = trans ? n : m;
+    g.in_len = trans ? m : n;
+    return g;
+}
+
+bwla_status bwla_gemv(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m, int64_t n,
+                      const void *A, int64_t lda, const void *x, bwla_dtype out_t, void *y, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (acc != BWLA_ACC_PLAIN && acc != BWLA_ACC_COMPENSATED)
+        return fail(BWLA_ERR_UNSUPPORTED, "accumulation mode %d", acc);
+    if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
+        return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
+    if (trans != 0 && trans != 1)
+        return fail(BWLA_ERR_INVALID_ARG, "trans %d", trans);
+    if (m < 0 || n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "negative size m=%lld n=%lld", (long long)m, (long long)n);
+    bwla_status st = out_type_ok(t, out_t);
+    if (st)
+        return st;
+    GemvPlan g = gemv_plan(layout, trans, m, n);
+    if (lda < std::max<int64_t>(1, g.K))
+        return fail(BWLA_ERR_INVALID_ARG, "lda %lld < %lld", (long long)lda, (long long)std::max<int64_t>(1, g.K));
+    if (g.out_len == 0)
+        return BWLA_OK;
+    if (!y)
+        return fail(BWLA_ERR_INVALID_ARG, "y is NULL");
+    const size_t es = dsize(t), os = out_t == BWLA_F64 ? 8 : 4;
+    if (g.in_len > 0 && (!A || !x))
+        return fail(BWLA_ERR_INVALID_ARG, "NULL A or x with a nonzero reduction length");
+    Span sy = span(y, g.out_len * os);
+    if (g.in_len > 0 && (overlaps(sy, span(A, matrix_bytes(g.L, g.K, lda, es))) ||
+                         overlaps(sy, span(x, g.in_len * es))))
+        return fail(BWLA_ERR_INVALID_ARG, "y overlaps A or x");
+    if (g.in_len == 0)
+        return hip_check(launch_fill_zero(y, g.out_len, out_t == BWLA_F64, (hipStream_t)stream), "fill launch");
+    const bool comp = acc == BWLA_ACC_COMPENSATED;
+    const int of64 = out_t == BWLA_F64;
+    hipStream_t s = (hipStream_t)stream;
+    if (g.rows) {
+        Cfg c = resolve_rows(t, g.L, g.K, A, lda, x);
+        const size_t need = ws_rows(c, g.L);
+        if (need && (!ws || ws_bytes < need))
+            return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+        hipError_t e = by_type(t, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            return launch_gemv_rows<T>(g.L, g.K, comp, A, lda, x, of64, y, ws, c, s);
+        });
+        return hip_check(e, "gemv (rows) launch");
+    }
+    Cfg c = resolve_cols(t, g.L, g.K, A, lda, x);
+    const size_t need = ws_cols(c, g.K);
+    if (need && (!ws || ws_bytes < need))
+        return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_gemv_cols<T>(g.L, g.K, comp, A, lda, x, of64, y, ws, c, s);
+    });
+    return hip_check(e, "gemv (cols) launch");
+}
+
+bwla_status bwla_ger(bwla_dtype t, bwla_layout layout, int64_t m, int64_t n, const void *u, const void *v,
+                     void *A, int64_t lda, void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
+        return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
+    if (m < 0 || n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "negative size m=%lld n=%lld", (long long)m, (long long)n);
+    const bool row_major = layout == BWLA_ROW_MAJOR;
+    const int64_t L = row_major ? m : n, K = row_major ? n : m;
+    if (lda < std::max<int64_t>(1, K))
+        return fail(BWLA_ERR_INVALID_ARG, "lda %lld < %lld", (long long)lda, (long long)std::max<int64_t>(1, K));
+    if (m == 0 || n == 0)
+        return BWLA_OK;
+    if (!u || !v || !A)
+        return fail(BWLA_ERR_INVALID_ARG, "NULL pointer");
+    const size_t es = dsize(t);
+    Span sa = span(A, matrix_bytes(L, K, lda, es));
+    if (overlaps(sa, span(u, m * es)) || overlaps(sa, span(v, n * es)))
+        return fail(BWLA_ERR_INVALID_ARG, "A overlaps u or v");
+    const void *a = row_major ? u : v; // per-line factor
+    const void *b = row_major ? v : u; // factor along the line
+    Cfg c = resolve_ger(t, L, K, a, b, A, lda);
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_ger<T>(L, K, a, b, A, lda, c, (hipStream_t)stream);
+    });
+    return hip_check(e, "ger launch");
+}
+
+bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha, const void *alpha_dev,
+                           void *x, const void *p, void *r, const void *q, bwla_dtype out_t, void *out,
+                           void *ws, size_t ws_bytes, void *stream)
+{
+    Cfg c = resolve_vector(BWLA_OP_DOT, t, n, {x, p, r, q}, 6);
+    const size_t need = n > 0 && c.grid > 1 ? ws_dot(c) : 0;
+    bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
+    if (st)
+        return st;
+    if (n == 0)
+        return hip_check(launch_fill_zero(out, 1, out_t == BWLA_F64, (hipStream_t)stream), "fill launch");
+    if (!x || !p || !r || !q)
+        return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
+    const size_t b = n * dsize(t);
+    Span sx = span(x, b), sp = span(p, b), sr = span(r, b), sq = span(q, b);
+    Span so = span(out, out_t == BWLA_F64 ? 8 : 4);
+    if (overlaps(sx, sr) || overlaps(sx, sp) || overlaps(sx, sq) || overlaps(sr, sp) || overlaps(sr, sq))
+        return fail(BWLA_ERR_INVALID_ARG, "the updated vectors x, r must not overlap each other or p, q");
+    if (overlaps(so, sx) || overlaps(so, sr) || overlaps(so, sp) || overlaps(so, sq))
+        return fail(BWLA_ERR_INVALID_ARG, "out overlaps a vector");
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_cg<T>(n, acc == BWLA_ACC_COMPENSATED, alpha, alpha_dev, x, p, r, q,
+                            out_t == BWLA_F64, out, ws, c, (hipStream_t)stream);
+    });
+    return hip_check(e, "cg update launch");
+}
+
+bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans,
+                                int64_t m, int64_t n, size_t *bytes)
+{
+    (void)acc;
+    if (!bytes)
+        return fail(BWLA_ERR_INVALID_ARG, "bytes is NULL");
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (m < 0 || n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "negative size");
+    *bytes = 0;
+    // The pack width a call ends up with depends on pointer alignment, and the
+    // default grid and split depend on the pack width, so size for the largest
+    // requirement over every width the call could use.  A fake address
+    // v*sizeof(T) (and line stride v) is aligned to exactly v elements.
+    size_t best = 0;
+    for (int v = 1; v <= 16; v <<= 1) {
+        const void *fake = (const void *)(uintptr_t)(v * dsize(t));
+        switch (op) {
+        case BWLA_OP_DOT:
+            best = std::max(best, ws_dot(resolve_vector(BWLA_OP_DOT, t, n, {fake}, 2)));
+            break;
+        case BWLA_OP_GEMV_ROWS:
+        case BWLA_OP_GEMV_COLS: {
+            if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
+                return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
+            GemvPlan g = gemv_plan(layout, trans, m, n);
+            if (g.rows)
+                best = std::max(best, ws_rows(resolve_rows(t, g.L, g.K, fake, v, fake), g.L));
+            else
+                best = std::max(best, ws_cols(resolve_cols(t, g.L, g.K, fake, v, fake), g.K));
+            break;
+        }
+        default:
+            break;
+        }
+    }
+    *bytes = best;
+    return BWLA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// configuration entry points
+// ---------------------------------------------------------------------------
+bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int size_class, const bwla_config *cfg)
+{
+    if (op < 0 || op >= BWLA_OP_COUNT)
+        return fail(BWLA_ERR_INVALID_ARG, "op %d", op);
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (size_class < -1 || size_class >= kClasses)
+        return fail(BWLA_ERR_INVALID_ARG, "size class %d", size_class);
+    bwla_config c{};
+    if (cfg) {
+        bwla_status st = check_cfg(*cfg);
+        if (st)
+            return st;
+        c = *cfg;
+    }
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    for (int k = 0; k < kClasses; ++k)
+        if (size_class < 0 || size_class == k)
+            g_table[op][t][k] = c;
+    return BWLA_OK;
+}
+
+bwla_status bwla_get_config(bwla_op op, bwla_dtype t, int64_t m, int64_t n, bwla_config *cfg)
+{
+    if (!cfg)
+        return fail(BWLA_ERR_INVALID_ARG, "cfg is NULL");
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (m < 0 || n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "negative size");
+    Cfg c;
+    switch (op) {
+    case BWLA_OP_COPY: c = resolve_vector(op, t, n, {}, 2); break;
+    case BWLA_OP_AXPBY: c = resolve_vector(op, t, n, {}, 3); break;
+    case BWLA_OP_DOT: c = resolve_vector(op, t, n, {}, 2); break;
+    case BWLA_OP_GEMV_ROWS: c = resolve_rows(t, m, n, nullptr, 0, nullptr); break;
+    case BWLA_OP_GEMV_COLS: c = resolve_cols(t, m, n, nullptr, 0, nullptr); break;
+    case BWLA_OP_GER: c = resolve_ger(t, m, n, nullptr, nullptr, nullptr, 0); break;
+    default: return fail(BWLA_ERR_INVALID_ARG, "op %d", op);
+    }
+    cfg->block = c.block;
+    cfg->vec = c.vec;
+    cfg->unroll = c.unroll;
+    cfg->grid = c.grid;
+    cfg->increment = c.inc;
+    cfg->rows = c.rows;
+    cfg->split = c.split;
+    return BWLA_OK;
+}
+
+bwla_status bwla_load_tuning(const char *path)
+{
+    if (!path)
+        return fail(BWLA_ERR_INVALID_ARG, "path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f)
+        return fail(BWLA_ERR_INVALID_ARG, "cannot open %s", path);
+    char line[512];
+    int lineno = 0;
+    struct Entry {
+        int op, t, k;
+        bwla_config c;
+    };
+    std::vector<Entry> entries;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        char *hash = strchr(line, '#');
+        if (hash)
+            *hash = 0;
+        Entry e{};
+        int got = sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &e.op, &e.t, &e.k, &e.c.block, &e.c.vec,
+                         &e.c.unroll, &e.c.grid, &e.c.increment, &e.c.rows, &e.c.split);
+        if (got <= 0)
+            continue; // blank or comment line
+        if (got != 10 || e.op < 0 || e.op >= BWLA_OP_COUNT || !valid_dtype(e.t) || e.k < -1 ||
+            e.k >= kClasses || check_cfg(e.c) != BWLA_OK) {
+            fclose(f);
+            return fail(BWLA_ERR_INVALID_ARG, "%s:%d: malformed tuning entry", path, lineno);
+        }
+        entries.push_back(e);
+    }
+    fclose(f);
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    for (const Entry &e : entries)
+        for (int k = 0; k < kClasses; ++k)
+            if (e.k < 0 || e.k == k)
+                g_table[e.op][e.t][k] = e.c;
+    return BWLA_OK;
+}
+
+} // extern "C"
+
+// ===========================================================================
+// batch plans
+// ===========================================================================
+struct bwla_batch_plan {
+    int t = 0, acc = 0, out_t = 0;
+    int device = 0;
+    int grid = 0, block = 256, vec = 1;
+    int64_t n_items = 0, n_dots = 0;
+    double bytes = 0;
+    BatchItem *d_items = nullptr;
+    BatchGemv *d_gemv = nullptr;
+    BatchDot *d_dots = nullptr;
+    double *d_partials = nullptr;
+    unsigned *d_counters = nullptr; // [0] = work counter, [1..] = per-dot tickets
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+void plan_free(bwla_batch_plan *p)
+{
+    if (!p)
+        return;
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    (void)hipFree(p->d_items);
+    (void)hipFree(p->d_gemv);
+    (void)hipFree(p->d_dots);
+    (void)hipFree(p->d_partials);
+    (void)hipFree(p->d_counters);
+    delete p;
+}
+
+hipError_t enqueue_batch(bwla_batch_plan *p, hipStream_t s)
+{
+    hipError_t e = launch_batch_reset(p->d_counters, 1 + p->n_dots, s);
+    if (e != hipSuccess)
+        return e;
+    BatchArgs a;
+    a.items = p->d_items;
+    a.n_items = p->n_items;
+    a.gemv = p->d_gemv;
+    a.dots = p->d_dots;
+    a.partials = p->d_partials;
+    a.dot_counters = p->d_counters + 1;
+    a.work_counter = p->d_counters;
+    a.out_f64 = p->out_t == BWLA_F64;
+    a.vec = p->vec;
+    return by_type(p->t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_batched<T>(a, p->acc == BWLA_ACC_COMPENSATED, p->grid, p->block, s);
+    });
+}
+} // namespace
+
+extern "C" {
+
+bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t, const bwla_gemv_desc *g,
+                                   int32_t ng, const bwla_dot_desc *d, int32_t nd, const bwla_config *cfg,
+                                   bwla_batch_plan **out)
+{
+    if (!out)
+        return fail(BWLA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (acc != BWLA_ACC_PLAIN && acc != BWLA_ACC_COMPENSATED)
+        return fail(BWLA_ERR_UNSUPPORTED, "accumulation mode %d", acc);
+    bwla_status st = out_type_ok(t, out_t);
+    if (st)
+        return st;
+    if (ng < 0 || nd < 0 || (ng > 0 && !g) || (nd > 0 && !d))
+        return fail(BWLA_ERR_INVALID_ARG, "bad descriptor arrays");
+    if (cfg && (st = check_cfg(*cfg)) != BWLA_OK)
+        return st;
+    const size_t es = dsize(t), os = out_t == BWLA_F64 ? 8 : 4;
+    bool aligned = true;
+    const int nv = native_vec(t);
+    for (int i = 0; i < ng; ++i) {
+        const bwla_gemv_desc &q = g[i];
+        if (q.m < 0 || q.n < 0 || q.lda < std::max<int64_t>(1, q.n))
+            return fail(BWLA_ERR_INVALID_ARG, "gemv %d: bad sizes or lda", i);
+        if (q.m > 0 && !q.y)
+            return fail(BWLA_ERR_INVALID_ARG, "gemv %d: y is NULL", i);
+        if (q.m > 0 && q.n > 0 && (!q.A || !q.x))
+            return fail(BWLA_ERR_INVALID_ARG, "gemv %d: NULL A or x", i);
+        if (q.m > 0 && q.n > 0) {
+            Span sy = span(q.y, q.m * os);
+            if (overlaps(sy, span(q.A, matrix_bytes(q.m, q.n, q.lda, es))) || overlaps(sy, span(q.x, q.n * es)))
+                return fail(BWLA_ERR_INVALID_ARG, "gemv %d: y overlaps A or x", i);
+            if (fit_vec(nv, es, {q.A, q.x}, q.lda) != nv)
+                aligned = false;
+        }
+    }
+    for (int i = 0; i < nd; ++i) {
+        const bwla_dot_desc &q = d[i];
+        if (q.n < 0 || !q.out || (q.n > 0 && (!q.x || !q.y)))
+            return fail(BWLA_ERR_INVALID_ARG, "dot %d: bad size or NULL pointer", i);
+        if (q.n > 0) {
+            Span so = span(q.out, os);
+            if (overlaps(so, span(q.x, q.n * es)) || overlaps(so, span(q.y, q.n * es)))
+                return fail(BWLA_ERR_INVALID_ARG, "dot %d: out overlaps an input", i);
+            if (fit_vec(nv, es, {q.x, q.y}) != nv)
+                aligned = false;
+        }
+    }
+    bwla_batch_plan *p = new bwla_batch_plan();
+    p->t = t;
+    p->acc = acc;
+    p->out_t = out_t;
+    p->vec = aligned ? nv : 1;
+    p->block = cfg && cfg->block ? cfg->block : 256;
+    (void)hipGetDevice(&p->device);
+
+    // work items, with their cost in bytes for the largest-first order
+    struct Work {
+        BatchItem it;
+        double cost;
+    };
+    std::vector<Work> work;
+    std::vector<BatchGemv> hg(ng);
+    std::vector<BatchDot> hd(nd);
+    const int64_t kTileElems = 1 << 17; // elements of A per GEMV row tile
+    const int64_t kChunk = 1 << 16;     // elements per dot chunk (a multiple of block*vec)
+    for (int i = 0; i < ng; ++i) {
+        const bwla_gemv_desc &q = g[i];
+        BatchGemv &b = hg[i];
+        b.A = q.A;
+        b.m = q.m;
+        b.n = q.n;
+        b.lda = q.lda;
+        b.x = q.x;
+        b.y = q.y;
+        int64_t packs = std::max<int64_t>(1, ceil_div(q.n, p->vec));
+        int lanes = 1;
+        while (lanes < 64 && lanes < packs)
+            lanes <<= 1;
+        b.lanes = lanes;
+        b.pad = 0;
+        if (q.m == 0)
+            continue;
+        const int64_t rpi = std::max<int64_t>(1, std::min<int64_t>(q.m, kTileElems / std::max<int64_t>(1, q.n)));
+        for (int64_t r0 = 0; r0 < q.m; r0 += rpi) {
+            Work w{};
+            w.it.kind = 0;
+            w.it.prob = i;
+            w.it.begin = r0;
+            w.it.end = std::min(q.m, r0 + rpi);
+            w.cost = (double)(w.it.end - w.it.begin) * std::max<int64_t>(q.n, 1) * es;
+            work.push_back(w);
+        }
+        p->bytes += (double)q.m * q.n * es + (double)q.n * es + (double)q.m * os;
+    }
+    int64_t slots = 0;
+    for (int i = 0; i < nd; ++i) {
+        const bwla_dot_desc &q = d[i];
+        BatchDot &b = hd[i];
+        b.x = q.x;
+        b.y = q.y;
+        b.n = q.n;
+        b.out = q.out;
+        b.slot0 = slots;
+        b.chunks = (int32_t)std::max<int64_t>(1, ceil_div(q.n, kChunk));
+        b.pad = 0;
+        for (int c = 0; c < b.chunks; ++c) {
+            Work w{};
+            w.it.kind = 1;
+            w.it.prob = i;
+            w.it.begin = (int64_t)c * kChunk;
+            w.it.end = std::min<int64_t>(q.n, (int64_t)(c + 1) * kChunk);
+            w.it.chunk = c;
+            w.cost = (double)std::max<int64_t>(1, w.it.end - w.it.begin) * 2 * es;
+            work.push_back(w);
+        }
+        slots += b.chunks;
+        p->bytes += 2.0 * q.n * es + os;
+    }
+    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+    std::vector<BatchItem> items(work.size());
+    for (size_t i = 0; i < work.size(); ++i)
+        items[i] = work[i].it;
+    p->n_items = (int64_t)items.size();
+    p->n_dots = nd;
+    const int64_t per_cu = std::max(1, 2048 / p->block);
+    int64_t grid = cfg && cfg->grid ? cfg->grid : (int64_t)device_cus() * per_cu;
+    p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, std::max<int64_t>(1, p->n_items)));
+
+    auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
+        if (bytes == 0)
+            bytes = 16;
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess)
+            return e;
+        if (src)
+            return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        return hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess)
+        e = alloc_copy((void **)&p->d_items, items.data(), items.size() * sizeof(BatchItem));
+    if (e == hipSuccess)
+        e = alloc_copy((void **)&p->d_gemv, hg.data(), hg.size() * sizeof(BatchGemv));
+    if (e == hipSuccess)
+        e = alloc_copy((void **)&p->d_dots, hd.data(), hd.size() * sizeof(BatchDot));
+    if (e == hipSuccess)
+        e = alloc_copy((void **)&p->d_partials, nullptr, (size_t)std::max<int64_t>(1, slots) * 2 * sizeof(double));
+    if (e == hipSuccess) {
+        std::vector<unsigned> zeros((size_t)(1 + nd), 0u);
+        e = alloc_copy((void **)&p->d_counters, zeros.data(), zeros.size() * sizeof(unsigned));
+    }
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_check(e, "batch plan allocation");
+    }
+    *out = p;
+    return BWLA_OK;
+}
+
+bwla_status bwla_batch_run(bwla_batch_plan *p, void *stream)
+{
+    if (!p)
+        return fail(BWLA_ERR_INVALID_ARG, "plan is NULL");
+    return hip_check(enqueue_batch(p, (hipStream_t)stream), "batched launch");
+}
+
+bwla_status bwla_batch_capture(bwla_batch_plan *p, void *stream)
+{
+    if (!p)
+        return fail(BWLA_ERR_INVALID_ARG, "plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (!s)
+        return fail(BWLA_ERR_NOT_CAPTURABLE, "the default stream cannot be captured; pass a created stream");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    bwla_status st = hip_check(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (st)
+        return st;
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(BWLA_ERR_NOT_CAPTURABLE, "stream is already capturing");
+    if (p->exec) {
+        (void)hipGraphExecDestroy(p->exec);
+        p->exec = nullptr;
+    }
+    if (p->graph) {
+        (void)hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    st = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (st)
+        return st;
+    hipError_t e = enqueue_batch(p, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return hip_check(e != hipSuccess ? e : e2, "batch capture");
+    }
+    p->graph = graph;
+    st = hip_check(hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    return st;
+}
+
+bwla_status bwla_batch_replay(bwla_batch_plan *p, void *stream)
+{
+    if (!p)
+        return fail(BWLA_ERR_INVALID_ARG, "plan is NULL");
+    if (!p->exec)
+        return fail(BWLA_ERR_INVALID_ARG, "plan has no captured graph");
+    return hip_check(hipGraphLaunch(p->exec, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+bwla_status bwla_batch_info(const bwla_batch_plan *p, int64_t *items, int32_t *grid, double *bytes)
+{
+    if (!p)
+        return fail(BWLA_ERR_INVALID_ARG, "plan is NULL");
+    if (items)
+        *items = p->n_items;
+    if (grid)
+        *grid = p->grid;
+    if (bytes)
+        *bytes = p->bytes;
+    return BWLA_OK;
+}
+
+void bwla_batch_plan_destroy(bwla_batch_plan *p) { plan_free(p); }
+
+} // extern "C"

@@ -1,0 +1,161 @@
+// batched.hip -- many uneven row-major GEMVs and dots in one persistent launch.
+//
+// The host flattens every problem into work items -- row tiles of a GEMV
+// (full row length) and fixed-size chunks of a dot -- ordered by decreasing
+// cost, and launches a grid sized to the machine.  Each work-group repeatedly
+// takes the next item from an atomic counter until the list is exhausted, so
+// every wave reaches the exit.  GEMV rows are handled by groups of G lanes
+// (G a power of two sized to the row length), reduced by butterfly exchanges
+// inside the group.  A dot chunk is reduced by the whole work-group; its
+// float64 partial goes to a slot of the dot, and the last chunk to finish
+// (atomic ticket) combines the dot's slots in chunk order.  Every result
+// depends only on its own problem's sizes, never on the batch order or on
+// which work-group ran which item.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace bwla {
+
+template <typename T, int V, bool COMP>
+__device__ __forceinline__ void gemv_tile(const BatchGemv &g, int64_t rb, int64_t re, int out_f64)
+{
+    using C = compute_t<T>;
+    constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int G = g.lanes;
+    const int rpw = 64 / G;
+    const int sub = lane / G, gl = lane - sub * G;
+    const T *A = (const T *)g.A;
+    const T *x = (const T *)g.x;
+    const int64_t K = g.n, kpack = K / V;
+    for (int64_t wbase = rb + (int64_t)wave * rpw; wbase < re; wbase += (int64_t)nw * rpw) {
+        const int64_t r = wbase + sub;
+        const int64_t rr = r < re ? r : re - 1;
+        const T *row = A + rr * g.lda;
+        Acc<C, COMP> acc;
+        for (int64_t p = gl; p < kpack; p += G) {
+            Pack<T, V> av = load_pack<T, V>(row + p * V), xv = load_pack<T, V>(x + p * V);
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                acc.template add_prod<EXACT>(widen(av.v[e]), widen(xv.v[e]));
+        }
+        for (int64_t k = kpack * V + gl; k < K; k += G)
+            acc.template add_prod<EXACT>(widen(row[k]), widen(x[k]));
+        DD d = acc.to_dd();
+        for (int m = G >> 1; m >= 1; m >>= 1)
+            d = combine<COMP>(d, shfl_xor_dd(d, m));
+        if (gl == 0 && r < re)
+            store_out(g.y, r, out_f64, d.hi + d.lo);
+    }
+}
+
+template <typename T, int V, bool COMP>
+__device__ __forceinline__ void dot_chunk(const BatchArgs &a, const BatchItem &w, DD *lds, int *flag)
+{
+    using C = compute_t<T>;
+    constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    const BatchDot &d = a.dots[w.prob];
+    const T *x = (const T *)d.x, *y = (const T *)d.y;
+    Acc<C, COMP> acc[2];
+    const int64_t pb = w.begin / V, pe = w.end / V; // chunk starts are pack-aligned
+    int64_t p = pb + threadIdx.x;
+    for (; p + blockDim.x < pe; p += 2 * (int64_t)blockDim.x) {
+        Pack<T, V> x0 = load_pack<T, V>(x + p * V), y0 = load_pack<T, V>(y + p * V);
+        Pack<T, V> x1 = load_pack<T, V>(x + (p + blockDim.x) * V), y1 = load_pack<T, V>(y + (p + blockDim.x) * V);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            acc[0].template add_prod<EXACT>(widen(x0.v[e]), widen(y0.v[e]));
+            acc[1].template add_prod<EXACT>(widen(x1.v[e]), widen(y1.v[e]));
+        }
+    }
+    for (; p < pe; p += blockDim.x) {
+        Pack<T, V> x0 = load_pack<T, V>(x + p * V), y0 = load_pack<T, V>(y + p * V);
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            acc[0].template add_prod<EXACT>(widen(x0.v[e]), widen(y0.v[e]));
+    }
+    const int64_t tail = w.end - pe * V;
+    if (threadIdx.x < tail)
+        acc[0].template add_prod<EXACT>(widen(x[pe * V + threadIdx.x]), widen(y[pe * V + threadIdx.x]));
+    DD v = combine<COMP>(acc[0].to_dd(), acc[1].to_dd());
+    v = block_sum<COMP>(v, lds);
+    if (d.chunks == 1) {
+        if (threadIdx.x == 0)
+            store_out(d.out, 0, a.out_f64, v.hi + v.lo);
+        return;
+    }
+    DD *slots = reinterpret_cast<DD *>(a.partials) + d.slot0;
+    if (threadIdx.x == 0)
+        slots[w.chunk] = v;
+    if (last_arrival(&a.dot_counters[w.prob], (unsigned)d.chunks, flag)) {
+        if (threadIdx.x == 0) {
+            DD t = slots[0];
+            for (int c = 1; c < d.chunks; ++c)
+                t = combine<COMP>(t, slots[c]);
+            store_out(d.out, 0, a.out_f64, t.hi + t.lo);
+        }
+    }
+}
+
+template <typename T, int V, bool COMP>
+__global__ __launch_bounds__(1024) void k_batched(BatchArgs a)
+{
+    __shared__ unsigned next;
+    __shared__ DD lds[16];
+    __shared__ int flag;
+    for (;;) {
+        if (threadIdx.x == 0)
+            next = atomicAdd(a.work_counter, 1u);
+        __syncthreads();
+        const int64_t it = next;
+        __syncthreads(); // everyone has read `next` before thread 0 overwrites it
+        if (it >= a.n_items)
+            break;
+        const BatchItem w = a.items[it];
+        if (w.kind == 0)
+            gemv_tile<T, V, COMP>(a.gemv[w.prob], w.begin, w.end, a.out_f64);
+        else
+            dot_chunk<T, V, COMP>(a, w, lds, &flag);
+    }
+}
+
+#if BWLA_T_IS_F64 // type-independent kernels live in the f64 object only
+__global__ void k_zero_counters(unsigned *c, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        c[i] = 0u;
+}
+#endif
+
+template <typename T>
+hipError_t launch_batched(const BatchArgs &a, bool comp, int grid, int block, hipStream_t s)
+{
+    constexpr int NATIVE = 16 / (int)sizeof(T);
+    auto go = [&](auto V) {
+        return with_bool(comp, [&](auto CP) {
+            hipLaunchKernelGGL((k_batched<T, V.value, CP.value>), dim3(grid), dim3(block), 0, s, a);
+            return hipGetLastError();
+        });
+    };
+    if (a.vec == 1)
+        return go(std::integral_constant<int, 1>{});
+    return go(std::integral_constant<int, NATIVE>{});
+}
+
+template hipError_t launch_batched<BWLA_T>(const BatchArgs &, bool, int, int, hipStream_t);
+
+#if BWLA_T_IS_F64
+hipError_t launch_batch_reset(unsigned *counters, int64_t count, hipStream_t s)
+{
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 1024)
+        blocks = 1024;
+    if (blocks < 1)
+        blocks = 1;
+    hipLaunchKernelGGL(k_zero_counters, dim3((unsigned)blocks), dim3(256), 0, s, counters, count);
+    return hipGetLastError();
+}
+#endif
+
+} // namespace bwla

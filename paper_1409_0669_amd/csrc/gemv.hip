@@ -1,0 +1,267 @@
+// gemv.hip -- dense matrix-vector products (paper Section 2: each output
+// entry is the inner product of one row with the right-hand side; the paper
+// notes other blockings are possible, and these kernels use two).
+//
+// A matrix is viewed as L "lines" of K contiguous elements, ld elements apart.
+// A row-major A has its rows as lines, a column-major A its columns, so:
+//   row-major  y = A x    and column-major y = A^T x  -> rows kernel
+//   row-major  y = A^T x  and column-major y = A x    -> cols kernel
+//
+// rows kernel: out[l] = sum_k A[l*ld + k] v[k].  A work-group owns R lines
+//   (and, with split > 1, one of `split` slices of their length).  Each
+//   thread loads a pack of v once into registers and reuses it for the R
+//   lines, so v is read from cache once per R lines of A.  The R sums are
+//   reduced across the wave (DPP) and across waves through LDS.  With split >
+//   1 the slices' float64 partials are combined in slice order by the last
+//   work-group of the line group to finish.
+//
+// cols kernel: out[k] = sum_l A[l*ld + k] v[l].  A work-group owns a tile of
+//   64*V consecutive outputs (V per lane, so each wave access is 64*V
+//   contiguous elements) and one of `split` slices of the lines; its waves
+//   take interleaved lines of the slice, U lines in flight.  The slice of v is
+//   staged in LDS (converted to the compute precision) and read as a
+//   wave-uniform broadcast.  Per-wave partial sums are combined through LDS in
+//   wave order; slices are combined in slice order by the last work-group of
+//   the tile.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace bwla {
+
+template <typename T, int V, int R, bool COMP>
+__global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const T *A, int64_t ld,
+                                                    const T *v, DD *partials, unsigned *counters,
+                                                    void *out, int out_f64, int split)
+{
+    using C = compute_t<T>;
+    constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    const int64_t group = blockIdx.x / split;
+    const int s = blockIdx.x - group * split;
+    const int64_t l0 = group * R;
+    const int nr = (int)(L - l0 < R ? L - l0 : R);
+    const T *row[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        row[r] = A + (l0 + (r < nr ? r : nr - 1)) * ld; // rows past L re-read the last one
+
+    const int64_t kpack = K / V;
+    const int64_t per = (kpack + split - 1) / split;
+    const int64_t pb = (int64_t)s * per;
+    const int64_t pe = pb + per < kpack ? pb + per : kpack;
+
+    Acc<C, COMP> acc[R];
+    for (int64_t p = pb + threadIdx.x; p < pe; p += blockDim.x) {
+        Pack<T, V> xv = load_pack<T, V>(v + p * V);
+        Pack<T, V> av[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            av[r] = load_pack<T, V>(row[r] + p * V);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                acc[r].template add_prod<EXACT>(widen(av[r].v[e]), widen(xv.v[e]));
+    }
+    const int64_t tail = K - kpack * V; // < V elements, taken by the last slice
+    if (s == split - 1 && threadIdx.x < tail) {
+        const int64_t k = kpack * V + threadIdx.x;
+        C xk = widen(v[k]);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            acc[r].template add_prod<EXACT>(widen(row[r][k]), xk);
+    }
+
+    __shared__ DD lds[16 * R];
+    __shared__ int flag;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        DD d = wave_sum<COMP>(acc[r].to_dd());
+        if (lane == 0)
+            lds[wave * R + r] = d;
+    }
+    __syncthreads();
+    DD t = {0.0, 0.0};
+    if (threadIdx.x < R) {
+        t = lds[threadIdx.x];
+        for (int w = 1; w < nw; ++w)
+            t = combine<COMP>(t, lds[w * R + threadIdx.x]);
+    }
+    if (split == 1) {
+        if (threadIdx.x < nr)
+            store_out(out, l0 + threadIdx.x, out_f64, t.hi + t.lo);
+        return;
+    }
+    if (threadIdx.x < R)
+        partials[(group * split + s) * R + threadIdx.x] = t;
+    if (last_arrival(&counters[group], split, &flag)) {
+        if (threadIdx.x < nr) {
+            DD u = partials[(group * split) * R + threadIdx.x];
+            for (int q = 1; q < split; ++q)
+                u = combine<COMP>(u, partials[(group * split + q) * R + threadIdx.x]);
+            store_out(out, l0 + threadIdx.x, out_f64, u.hi + u.lo);
+        }
+    }
+}
+
+template <typename T, int V, int U, bool COMP>
+__global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const T *A, int64_t ld,
+                                                    const T *v, DD *partials, unsigned *counters,
+                                                    void *out, int out_f64, int split)
+{
+    using C = compute_t<T>;
+    constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    constexpr int TK = 64 * V;
+    const int64_t tile = blockIdx.x / split;
+    const int s = blockIdx.x - tile * split;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int64_t k0 = tile * TK + (int64_t)lane * V;
+    const bool full = k0 + V <= K;
+    const int64_t per = (L + split - 1) / split;
+    const int64_t lb = (int64_t)s * per;
+    const int64_t le = lb + per < L ? lb + per : L;
+
+    // One LDS buffer serves first as the staged slice of v and then as the
+    // exchange area of the cross-wave combine.
+    constexpr int kStageBytes = kColsStageLines * (int)sizeof(C);
+    constexpr int kRedBytes = TK * (int)sizeof(DD);
+    __shared__ __attribute__((aligned(16))) char smem[kStageBytes > kRedBytes ? kStageBytes : kRedBytes];
+    __shared__ int flag;
+    C *vs = reinterpret_cast<C *>(smem);
+    Acc<C, COMP> acc[V];
+
+    for (int64_t t0 = lb; t0 < le; t0 += kColsStageLines) {
+        const int tn = (int)(le - t0 < kColsStageLines ? le - t0 : kColsStageLines);
+        __syncthreads();
+        for (int i = threadIdx.x; i < tn; i += blockDim.x)
+            vs[i] = widen(v[t0 + i]);
+        __syncthreads();
+        const T *base = A + t0 * ld + k0;
+        int j = wave;
+        if (full) {
+            for (; j + (U - 1) * nw < tn; j += U * nw) {
+                Pack<T, V> a[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    a[u] = load_pack<T, V>(base + (int64_t)(j + u * nw) * ld);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const C xl = vs[j + u * nw];
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        acc[e].template add_prod<EXACT>(widen(a[u].v[e]), xl);
+                }
+            }
+            for (; j < tn; j += nw) {
+                Pack<T, V> a = load_pack<T, V>(base + (int64_t)j * ld);
+                const C xl = vs[j];
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    acc[e].template add_prod<EXACT>(widen(a.v[e]), xl);
+            }
+        } else if (k0 < K) {
+            for (; j < tn; j += nw) {
+                const C xl = vs[j];
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if (k0 + e < K)
+                        acc[e].template add_prod<EXACT>(widen(base[(int64_t)j * ld + e]), xl);
+            }
+        }
+    }
+
+    // combine the waves' partial sums in wave order through LDS
+    __syncthreads();
+    DD *red = reinterpret_cast<DD *>(smem);
+    DD d[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+        d[e] = acc[e].to_dd();
+    for (int w = 1; w < nw; ++w) {
+        if (wave == w)
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                red[lane * V + e] = d[e];
+        __syncthreads();
+        if (wave == 0)
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                d[e] = combine<COMP>(d[e], red[lane * V + e]);
+        __syncthreads();
+    }
+    if (split == 1) {
+        if (wave == 0)
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (k0 + e < K)
+                    store_out(out, k0 + e, out_f64, d[e].hi + d[e].lo);
+        return;
+    }
+    if (wave == 0)
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            partials[(tile * split + s) * TK + lane * V + e] = d[e];
+    if (last_arrival(&counters[tile], split, &flag)) {
+        if (wave == 0) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                DD u = partials[(tile * split) * TK + lane * V + e];
+                for (int q = 1; q < split; ++q)
+                    u = combine<COMP>(u, partials[(tile * split + q) * TK + lane * V + e]);
+                if (k0 + e < K)
+                    store_out(out, k0 + e, out_f64, u.hi + u.lo);
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_gemv_rows(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
+                            const void *v, int out_f64, void *out, void *ws, const Cfg &c,
+                            hipStream_t s)
+{
+    unsigned *counters = (unsigned *)ws;
+    DD *partials = ws ? (DD *)((char *)ws + kCounterBytes) : nullptr;
+    return with_vec(c.vec, [&](auto V) {
+        return with_rows(c.rows, [&](auto R) {
+            return with_bool(comp, [&](auto CP) {
+                const int64_t groups = (L + R.value - 1) / R.value;
+                hipLaunchKernelGGL((k_gemv_rows<T, V.value, R.value, CP.value>),
+                                   dim3((unsigned)(groups * c.split)), dim3(c.block), 0, s, L, K,
+                                   (const T *)A, ld, (const T *)v, partials, counters, out, out_f64,
+                                   c.split);
+                return hipGetLastError();
+            });
+        });
+    });
+}
+
+template <typename T>
+hipError_t launch_gemv_cols(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
+                            const void *v, int out_f64, void *out, void *ws, const Cfg &c,
+                            hipStream_t s)
+{
+    unsigned *counters = (unsigned *)ws;
+    DD *partials = ws ? (DD *)((char *)ws + kCounterBytes) : nullptr;
+    return with_vec(c.vec, [&](auto V) {
+        return with_unroll(c.unroll, [&](auto U) {
+            return with_bool(comp, [&](auto CP) {
+                const int64_t tiles = (K + 64 * V.value - 1) / (64 * V.value);
+                hipLaunchKernelGGL((k_gemv_cols<T, V.value, U.value, CP.value>),
+                                   dim3((unsigned)(tiles * c.split)), dim3(c.block), 0, s, L, K,
+                                   (const T *)A, ld, (const T *)v, partials, counters, out, out_f64,
+                                   c.split);
+                return hipGetLastError();
+            });
+        });
+    });
+}
+
+template hipError_t launch_gemv_rows<BWLA_T>(int64_t, int64_t, bool, const void *, int64_t,
+                                             const void *, int, void *, void *, const Cfg &,
+                                             hipStream_t);
+template hipError_t launch_gemv_cols<BWLA_T>(int64_t, int64_t, bool, const void *, int64_t,
+                                             const void *, int, void *, void *, const Cfg &,
+                                             hipStream_t);
+
+} // namespace bwla

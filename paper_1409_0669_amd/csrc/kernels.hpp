@@ -1,0 +1,138 @@
+// kernels.hpp -- host-side launchers of the gfx950 kernels (internal).  Each
+// kernel source is compiled once per storage type; the API layer validates
+// arguments and resolves the configuration before calling these.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+
+namespace bwla {
+
+// Resolved kernel configuration (no zero fields left).
+struct Cfg {
+    int block, vec, unroll, grid, inc, rows, split;
+};
+
+// Workspace layout of the reductions: a fixed counter region first (left
+// zero by every call), float64 partials after it.
+constexpr size_t kCounterBytes = 65536;
+constexpr int64_t kMaxCounters = (int64_t)(kCounterBytes / sizeof(unsigned));
+constexpr int kColsStageLines = 2048; // x entries staged in LDS per pass (cols kernel)
+
+// Map a runtime value onto a compile-time constant for template dispatch.
+template <typename F> hipError_t with_vec(int v, F &&f)
+{
+    switch (v) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    }
+    return hipErrorInvalidValue;
+}
+template <typename F> hipError_t with_unroll(int u, F &&f)
+{
+    switch (u) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    }
+    return hipErrorInvalidValue;
+}
+template <typename F> hipError_t with_rows(int r, F &&f)
+{
+    switch (r) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    }
+    return hipErrorInvalidValue;
+}
+template <typename F> hipError_t with_bool(bool b, F &&f)
+{
+    if (b)
+        return f(std::integral_constant<bool, true>{});
+    return f(std::integral_constant<bool, false>{});
+}
+
+// --- streaming: copy, axpby, fused CG update --------------------------------
+template <typename T>
+hipError_t launch_copy(int64_t n, const void *y, void *x, const Cfg &c, hipStream_t s);
+template <typename T>
+hipError_t launch_axpby(int64_t n, double alpha, const void *adev, const void *y, double beta,
+                        const void *bdev, const void *z, void *x, const Cfg &c, hipStream_t s);
+template <typename T>
+hipError_t launch_cg(int64_t n, bool comp, double alpha, const void *adev, void *x, const void *p,
+                     void *r, const void *q, int out_f64, void *out, void *ws, const Cfg &c,
+                     hipStream_t s);
+
+// --- reductions: dot and nrm2 ----------------------------------------------
+// Partials needed: c.grid DD pairs.
+template <typename T>
+hipError_t launch_dot(int64_t n, bool comp, bool square, const void *x, const void *y, int out_f64,
+                      void *out, void *ws, const Cfg &c, hipStream_t s);
+
+// --- matrix-vector ---------------------------------------------------------
+// A line is a contiguous run of K elements; lines are ld apart.
+//   rows kernel:  out[l] = sum_k A[l*ld + k] * v[k]     (l < L)
+//   cols kernel:  out[k] = sum_l A[l*ld + k] * v[l]     (k < K)
+template <typename T>
+hipError_t launch_gemv_rows(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
+                            const void *v, int out_f64, void *out, void *ws, const Cfg &c,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_gemv_cols(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
+                            const void *v, int out_f64, void *out, void *ws, const Cfg &c,
+                            hipStream_t s);
+// --- rank-1 overwrite: A[l*ld + k] = a[l] * b[k] ---------------------------
+template <typename T>
+hipError_t launch_ger(int64_t L, int64_t K, const void *a, const void *b, void *A, int64_t ld,
+                      const Cfg &c, hipStream_t s);
+
+// --- zero fill of `count` outputs of float64 or float32 ---------------------
+hipError_t launch_fill_zero(void *out, int64_t count, int out_f64, hipStream_t s);
+
+// --- batched persistent kernel ----------------------------------------------
+struct BatchItem {
+    int32_t kind;   // 0 = GEMV row tile, 1 = dot chunk
+    int32_t prob;   // problem index within its kind
+    int64_t begin;  // first row (GEMV) or first element (dot)
+    int64_t end;    // one past the last row / element
+    int32_t chunk;  // chunk index within the dot
+    int32_t pad;
+};
+struct BatchGemv {
+    const void *A;
+    int64_t m, n, lda;
+    const void *x;
+    void *y;
+    int32_t lanes; // lanes per row (power of two, <= 64)
+    int32_t pad;
+};
+struct BatchDot {
+    const void *x, *y;
+    int64_t n;
+    void *out;
+    int64_t slot0;  // first partial slot of this dot
+    int32_t chunks; // number of chunks
+    int32_t pad;
+};
+struct BatchArgs {
+    const BatchItem *items;
+    int64_t n_items;
+    const BatchGemv *gemv;
+    const BatchDot *dots;
+    double *partials;       // 2 doubles per dot chunk
+    unsigned *dot_counters; // one per dot
+    unsigned *work_counter; // next item to take
+    int out_f64;
+    int vec;                // elements per pack: 1 or 16 bytes' worth
+};
+template <typename T>
+hipError_t launch_batched(const BatchArgs &a, bool comp, int grid, int block, hipStream_t s);
+hipError_t launch_batch_reset(unsigned *counters, int64_t count, hipStream_t s);
+
+} // namespace bwla

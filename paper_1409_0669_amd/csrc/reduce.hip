@@ -1,0 +1,148 @@
+// reduce.hip -- inner product <x, y> and Euclidean norm sqrt(<x, x>) (paper
+// Section 2: inner product with a work-group reduction in local memory).
+//
+// Stage 1: every thread accumulates its packs (same pack walk and increment
+// schemes as the streaming kernels) into U independent accumulators in the
+// compute precision, plain or compensated.  The accumulators leave the thread
+// as float64 (pairs when compensated), are summed across the wave with DPP and
+// cross-row exchanges, across the work-group through LDS, and the work-group
+// partial is written to the workspace.  Stage 2: the last work-group to finish
+// (atomic ticket) sums all partials in index order and writes the scalar.  No
+// floating-point atomics are used, so the result is deterministic for a given
+// configuration.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace bwla {
+
+template <typename T, int V, int U, bool COMP, bool SQ>
+__global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y, DD *partials,
+                                              unsigned *counter, void *out, int out_f64, int inc)
+{
+    using C = compute_t<T>;
+    constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    Acc<C, COMP> acc[U];
+    const int64_t npack = n / V;
+    int64_t begin, stride, end;
+    if (inc == 0) {
+        begin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        stride = (int64_t)gridDim.x * blockDim.x;
+        end = npack;
+    } else {
+        int64_t per = (npack + gridDim.x - 1) / gridDim.x;
+        per = (per + blockDim.x - 1) / blockDim.x * blockDim.x;
+        int64_t b = (int64_t)blockIdx.x * per;
+        begin = b + threadIdx.x;
+        stride = blockDim.x;
+        end = b + per < npack ? b + per : npack;
+    }
+    int64_t p = begin;
+    for (; p + (U - 1) * stride < end; p += U * stride) {
+        Pack<T, V> vx[U], vy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vx[u] = load_pack<T, V>(x + (p + u * stride) * V);
+            if constexpr (!SQ)
+                vy[u] = load_pack<T, V>(y + (p + u * stride) * V);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                C a = widen(vx[u].v[e]);
+                C b = SQ ? a : widen(vy[u].v[e]);
+                acc[u].template add_prod<EXACT>(a, b);
+            }
+    }
+    for (; p < end; p += stride) {
+        Pack<T, V> vx = load_pack<T, V>(x + p * V), vy;
+        if constexpr (!SQ)
+            vy = load_pack<T, V>(y + p * V);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            C a = widen(vx.v[e]);
+            C b = SQ ? a : widen(vy.v[e]);
+            acc[0].template add_prod<EXACT>(a, b);
+        }
+    }
+    const int64_t tail = n - npack * V;
+    if (blockIdx.x == 0 && threadIdx.x < tail) {
+        C a = widen(x[npack * V + threadIdx.x]);
+        C b = SQ ? a : widen(y[npack * V + threadIdx.x]);
+        acc[0].template add_prod<EXACT>(a, b);
+    }
+    DD v = acc[0].to_dd();
+#pragma unroll
+    for (int u = 1; u < U; ++u)
+        v = combine<COMP>(v, acc[u].to_dd());
+
+    __shared__ DD lds[16];
+    __shared__ int flag;
+    DD bs = block_sum<COMP>(v, lds);
+    if (gridDim.x == 1) {
+        if (threadIdx.x == 0) {
+            double r = bs.hi + bs.lo;
+            store_out(out, 0, out_f64, SQ ? __builtin_sqrt(r) : r);
+        }
+        return;
+    }
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = bs;
+    if (last_arrival(counter, gridDim.x, &flag)) {
+        DD t = {0.0, 0.0};
+        for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x)
+            t = combine<COMP>(t, partials[k]);
+        t = block_sum<COMP>(t, lds);
+        if (threadIdx.x == 0) {
+            double r = t.hi + t.lo;
+            store_out(out, 0, out_f64, SQ ? __builtin_sqrt(r) : r);
+        }
+    }
+}
+
+#if BWLA_T_IS_F64 // type-independent kernels live in the f64 object only
+__global__ void k_fill_zero(void *out, int64_t count, int out_f64)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        store_out(out, i, out_f64, 0.0);
+}
+#endif
+
+template <typename T>
+hipError_t launch_dot(int64_t n, bool comp, bool square, const void *x, const void *y, int out_f64,
+                      void *out, void *ws, const Cfg &c, hipStream_t s)
+{
+    unsigned *counter = (unsigned *)ws;
+    DD *partials = (DD *)((char *)ws + kCounterBytes);
+    return with_vec(c.vec, [&](auto V) {
+        return with_unroll(c.unroll, [&](auto U) {
+            return with_bool(comp, [&](auto CP) {
+                return with_bool(square, [&](auto SQ) {
+                    hipLaunchKernelGGL((k_dot<T, V.value, U.value, CP.value, SQ.value>), dim3(c.grid),
+                                       dim3(c.block), 0, s, n, (const T *)x, (const T *)y, partials,
+                                       counter, out, out_f64, c.inc);
+                    return hipGetLastError();
+                });
+            });
+        });
+    });
+}
+
+template hipError_t launch_dot<BWLA_T>(int64_t, bool, bool, const void *, const void *, int, void *,
+                                       void *, const Cfg &, hipStream_t);
+
+#if BWLA_T_IS_F64
+hipError_t launch_fill_zero(void *out, int64_t count, int out_f64, hipStream_t s)
+{
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (blocks < 1)
+        blocks = 1;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, out, count, out_f64);
+    return hipGetLastError();
+}
+#endif
+
+} // namespace bwla

@@ -1,0 +1,278 @@
+"""Torch-facing calls of the library: tensors in, tensors out.
+
+PyTorch supplies device memory and the current stream; each function checks
+its tensors, then passes raw device pointers, sizes and the stream to the C
+ABI, where the HIP kernels do all the work.  Vectors must be contiguous; no
+silent copies are made.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import torch
+
+from . import _lib as L
+from ._lib import BwlaError, check, lib
+
+_DTYPE = {torch.float64: L.F64, torch.float32: L.F32, torch.bfloat16: L.BF16}
+_OUT_TORCH = {L.F64: torch.float64, L.F32: torch.float32}
+_ACC = {"plain": L.ACC_PLAIN, "compensated": L.ACC_COMPENSATED, L.ACC_PLAIN: L.ACC_PLAIN,
+        L.ACC_COMPENSATED: L.ACC_COMPENSATED}
+
+
+def dtype_code(t: torch.dtype) -> int:
+    try:
+        return _DTYPE[t]
+    except KeyError:
+        raise BwlaError(L.ERR_UNSUPPORTED, "dtype %s (supported: float64, float32, bfloat16)" % t)
+
+
+def compute_dtype(t: torch.dtype) -> torch.dtype:
+    """Torch dtype of the compute precision of a storage dtype."""
+    return torch.float64 if t == torch.float64 else torch.float32
+
+
+def default_out_dtype(t: torch.dtype) -> torch.dtype:
+    return torch.float64 if t == torch.float64 else torch.float32
+
+
+def _stream(device=None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _vec(t: torch.Tensor, name: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise BwlaError(L.ERR_INVALID_ARG, "%s must be a GPU tensor" % name)
+    if t.dim() != 1 or not t.is_contiguous():
+        raise BwlaError(L.ERR_INVALID_ARG, "%s must be a contiguous 1-D tensor" % name)
+
+
+def _same(dtype, device, *ts) -> None:
+    for t in ts:
+        if t.dtype != dtype:
+            raise BwlaError(L.ERR_INVALID_ARG, "dtype mismatch: %s vs %s" % (t.dtype, dtype))
+        if t.device != device:
+            raise BwlaError(L.ERR_INVALID_ARG, "device mismatch: %s vs %s" % (t.device, device))
+
+
+# ---------------------------------------------------------------------------
+# workspace: one zero-initialised buffer per (device, stream), grown on demand
+# ---------------------------------------------------------------------------
+_ws_lock = threading.Lock()
+_ws: dict = {}
+
+
+def workspace(nbytes: int, device: torch.device) -> torch.Tensor | None:
+    """A zero-filled workspace of at least ``nbytes`` for the current stream.
+    The library leaves its counter region zero after each call, so the buffer
+    is reused; it is reallocated (zero-filled) only when it must grow.  Grow it
+    before any graph capture with :func:`reserve_workspace`."""
+    if nbytes == 0:
+        return None
+    key = (device.index, torch.cuda.current_stream(device).cuda_stream)
+    with _ws_lock:
+        buf = _ws.get(key)
+        if buf is None or buf.numel() < nbytes:
+            size = max(nbytes, L.WS_COUNTER_BYTES + (1 << 20))
+            size = (size + (1 << 20) - 1) >> 20 << 20
+            buf = torch.zeros(size, dtype=torch.uint8, device=device)
+            _ws[key] = buf
+        return buf
+
+
+def reserve_workspace(nbytes: int, device=None) -> None:
+    workspace(nbytes, torch.device("cuda", torch.cuda.current_device() if device is None else device))
+
+
+def _ws_ptr(buf):
+    return (ctypes.c_void_p(buf.data_ptr()), buf.numel()) if buf is not None else (None, 0)
+
+
+def workspace_size(op: int, dtype: torch.dtype, acc="plain", layout: int = L.ROW_MAJOR, trans: int = 0,
+                   m: int = 0, n: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib.bwla_workspace_size(op, dtype_code(dtype), _ACC[acc], layout, trans, m, n, ctypes.byref(out)))
+    return out.value
+
+
+# ---------------------------------------------------------------------------
+# operations
+# ---------------------------------------------------------------------------
+def copy(y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """x <- y."""
+    _vec(y, "y")
+    x = torch.empty_like(y) if out is None else out
+    _vec(x, "out")
+    _same(y.dtype, y.device, x)
+    if x.numel() != y.numel():
+        raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
+    check(lib.bwla_copy(dtype_code(y.dtype), y.numel(), y.data_ptr(), x.data_ptr(), _stream(y.device)))
+    return x
+
+
+def axpby(alpha: float, y: torch.Tensor, beta: float, z: torch.Tensor, out: torch.Tensor | None = None,
+          alpha_dev: torch.Tensor | None = None, beta_dev: torch.Tensor | None = None) -> torch.Tensor:
+    """x <- alpha*y + beta*z, computed as RN(fma(a, y, RN(b*z))) in the compute
+    precision.  ``out`` may be ``y`` or ``z`` (in-place).  ``alpha_dev`` /
+    ``beta_dev``: optional one-element device tensors of the compute dtype that
+    multiply the host factors."""
+    _vec(y, "y")
+    _vec(z, "z")
+    _same(y.dtype, y.device, z)
+    x = torch.empty_like(y) if out is None else out
+    _vec(x, "out")
+    _same(y.dtype, y.device, x)
+    if not (x.numel() == y.numel() == z.numel()):
+        raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
+    cd = compute_dtype(y.dtype)
+    for name, s in (("alpha_dev", alpha_dev), ("beta_dev", beta_dev)):
+        if s is not None and (s.dtype != cd or s.numel() != 1 or s.device != y.device):
+            raise BwlaError(L.ERR_INVALID_ARG, "%s must be one %s element on %s" % (name, cd, y.device))
+    check(lib.bwla_axpby(dtype_code(y.dtype), y.numel(), float(alpha),
+                         None if alpha_dev is None else alpha_dev.data_ptr(), y.data_ptr(), float(beta),
+                         None if beta_dev is None else beta_dev.data_ptr(), z.data_ptr(), x.data_ptr(),
+                         _stream(y.device)))
+    return x
+
+
+def _scalar_out(dtype, out_dtype, device, out):
+    od = default_out_dtype(dtype) if out_dtype is None else out_dtype
+    if od not in (torch.float64, torch.float32):
+        raise BwlaError(L.ERR_UNSUPPORTED, "output dtype %s" % od)
+    if out is None:
+        out = torch.empty((), dtype=od, device=device)
+    elif out.dtype != od or out.numel() != 1 or out.device != device:
+        raise BwlaError(L.ERR_INVALID_ARG, "out must be one %s element on %s" % (od, device))
+    return out, _DTYPE[od]
+
+
+def dot(x: torch.Tensor, y: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
+        out: torch.Tensor | None = None) -> torch.Tensor:
+    """<x, y> as a 0-dim device tensor (float64 for f64 input, float32 by
+    default otherwise)."""
+    _vec(x, "x")
+    _vec(y, "y")
+    _same(x.dtype, x.device, y)
+    if x.numel() != y.numel():
+        raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
+    out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
+    ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
+    check(lib.bwla_dot(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), y.data_ptr(), oc,
+                       out.data_ptr(), ws, wsn, _stream(x.device)))
+    return out
+
+
+def nrm2(x: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
+         out: torch.Tensor | None = None) -> torch.Tensor:
+    """sqrt(<x, x>) as a 0-dim device tensor."""
+    _vec(x, "x")
+    out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
+    ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
+    check(lib.bwla_nrm2(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), oc, out.data_ptr(), ws, wsn,
+                        _stream(x.device)))
+    return out
+
+
+def matrix_layout(A: torch.Tensor):
+    """(layout, lda) of a 2-D tensor whose rows or columns are contiguous."""
+    if A.dim() != 2:
+        raise BwlaError(L.ERR_INVALID_ARG, "A must be 2-D")
+    m, n = A.shape
+    s0, s1 = A.stride()
+    if s1 == 1 and (s0 >= max(1, n) or m <= 1):
+        return L.ROW_MAJOR, max(s0, n, 1)
+    if s0 == 1 and (s1 >= max(1, m) or n <= 1):
+        return L.COL_MAJOR, max(s1, m, 1)
+    raise BwlaError(L.ERR_INVALID_ARG, "A must have contiguous rows or columns (strides %s)" % (A.stride(),))
+
+
+def gemv(A: torch.Tensor, x: torch.Tensor, trans: bool = False, acc="plain",
+         out_dtype: torch.dtype | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """y = op(A) x with op(A) = A or A^T.  The layout (row- or column-major,
+    with leading dimension) is read from A's strides."""
+    if not A.is_cuda:
+        raise BwlaError(L.ERR_INVALID_ARG, "A must be a GPU tensor")
+    layout, lda = matrix_layout(A)
+    _vec(x, "x")
+    _same(A.dtype, A.device, x)
+    m, n = A.shape
+    out_len, in_len = (n, m) if trans else (m, n)
+    if x.numel() != in_len:
+        raise BwlaError(L.ERR_INVALID_ARG, "x has %d entries, op(A) has %d columns" % (x.numel(), in_len))
+    od = default_out_dtype(A.dtype) if out_dtype is None else out_dtype
+    if od not in (torch.float64, torch.float32):
+        raise BwlaError(L.ERR_UNSUPPORTED, "output dtype %s" % od)
+    y = torch.empty(out_len, dtype=od, device=A.device) if out is None else out
+    _vec(y, "out")
+    if y.numel() != out_len or y.dtype != od:
+        raise BwlaError(L.ERR_INVALID_ARG, "out must have %d %s entries" % (out_len, od))
+    op = L.OP_GEMV_ROWS
+    ws, wsn = _ws_ptr(workspace(workspace_size(op, A.dtype, acc, layout, int(trans), m, n), A.device))
+    check(lib.bwla_gemv(dtype_code(A.dtype), _ACC[acc], layout, int(trans), m, n, A.data_ptr(), lda,
+                        x.data_ptr(), _DTYPE[od], y.data_ptr(), ws, wsn, _stream(A.device)))
+    return y
+
+
+def ger(u: torch.Tensor, v: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """A <- u v^T (overwrite), every entry rounded once to A's dtype.  ``out``
+    is the m x n matrix to overwrite; its layout is read from its strides."""
+    _vec(u, "u")
+    _vec(v, "v")
+    _same(out.dtype, out.device, u, v)
+    layout, lda = matrix_layout(out)
+    m, n = out.shape
+    if u.numel() != m or v.numel() != n:
+        raise BwlaError(L.ERR_INVALID_ARG, "u, v must have %d and %d entries" % (m, n))
+    check(lib.bwla_ger(dtype_code(out.dtype), layout, m, n, u.data_ptr(), v.data_ptr(), out.data_ptr(), lda,
+                       _stream(out.device)))
+    return out
+
+
+def cg_update(alpha: float, x: torch.Tensor, p: torch.Tensor, r: torch.Tensor, q: torch.Tensor, acc="plain",
+              out_dtype: torch.dtype | None = None, alpha_dev: torch.Tensor | None = None,
+              out: torch.Tensor | None = None) -> torch.Tensor:
+    """One fused pass: x += a p, r -= a q, returns <r, r> (0-dim tensor)."""
+    for name, t in (("x", x), ("p", p), ("r", r), ("q", q)):
+        _vec(t, name)
+    _same(x.dtype, x.device, p, r, q)
+    if not (x.numel() == p.numel() == r.numel() == q.numel()):
+        raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
+    if alpha_dev is not None and (alpha_dev.dtype != compute_dtype(x.dtype) or alpha_dev.numel() != 1):
+        raise BwlaError(L.ERR_INVALID_ARG, "alpha_dev must be one %s element" % compute_dtype(x.dtype))
+    out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
+    ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
+    check(lib.bwla_cg_update(dtype_code(x.dtype), _ACC[acc], x.numel(), float(alpha),
+                             None if alpha_dev is None else alpha_dev.data_ptr(), x.data_ptr(), p.data_ptr(),
+                             r.data_ptr(), q.data_ptr(), oc, out.data_ptr(), ws, wsn, _stream(x.device)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# configuration
+# ---------------------------------------------------------------------------
+def set_config(op: int, dtype: torch.dtype, size_class: int = -1, **fields) -> None:
+    """Set the configuration of (op, dtype, size class); no fields = defaults."""
+    if fields:
+        c = L.Config(**{k: int(v) for k, v in fields.items()})
+        check(lib.bwla_set_config(op, dtype_code(dtype), size_class, ctypes.byref(c)))
+    else:
+        check(lib.bwla_set_config(op, dtype_code(dtype), size_class, None))
+
+
+def get_config(op: int, dtype: torch.dtype, m: int = 0, n: int = 0) -> dict:
+    c = L.Config()
+    check(lib.bwla_get_config(op, dtype_code(dtype), m, n, ctypes.byref(c)))
+    return c.as_dict()
+
+
+def load_tuning(path: str) -> None:
+    check(lib.bwla_load_tuning(path.encode()))
+
+
+def reset_config() -> None:
+    for op in range(6):
+        for t in (torch.float64, torch.float32, torch.bfloat16):
+            set_config(op, t)

@@ -1,0 +1,47 @@
+"""Acceptance criteria of the parity tests (test helper).
+
+* Single-rounding operations (copy, scaled addition, rank-1 overwrite, dot
+  backward): bitwise equal to the oracle (0 ULP) in matching precision.
+* Reductions: many results are correct (the summation order is free), so they
+  are compared within a tolerance: 1e-12 for float64 storage, 1e-5 for float32
+  and bfloat16 storage (bf16 inputs compared on their quantised values).
+  - dot / nrm2: |got - ref| <= tol * |ref|; when the exact value is 0 by
+    construction, normwise |got - ref| <= tol * sum |x_i y_i|.
+  - GEMV: per output, |got_i - ref_i| <= tol * (|A| |x|)_i (componentwise,
+    condition-scaled), and max |got - ref| <= tol * max |ref|.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-5}
+
+
+def check_scalar(got: float, ref: float, absum: float, tol: float, what: str = "") -> None:
+    err = abs(got - ref)
+    if ref != 0.0:
+        assert err <= tol * abs(ref), "%s: rel err %.3e > %.1e (got %r ref %r)" % (what, err / abs(ref), tol, got, ref)
+    else:
+        assert err <= tol * max(absum, 1e-300), "%s: normwise err %.3e (got %r)" % (what, err, got)
+
+
+def check_vector(got: np.ndarray, ref: np.ndarray, scale: np.ndarray, tol: float, what: str = "") -> None:
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    if ref.size == 0:
+        return
+    err = np.abs(got - ref)
+    bad = err > tol * np.maximum(scale, 1e-300)
+    assert not bad.any(), "%s: %d entries beyond componentwise tol %.1e; worst %.3e at %d" % (
+        what, int(bad.sum()), tol, float((err / np.maximum(scale, 1e-300)).max()),
+        int(np.argmax(err / np.maximum(scale, 1e-300))))
+    rmax = float(np.abs(ref).max())
+    if rmax > 0:
+        assert float(err.max()) <= tol * rmax, "%s: normwise err %.3e" % (what, float(err.max()) / rmax)
+
+
+def bitwise_equal(got: np.ndarray, ref: np.ndarray) -> bool:
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return got.shape == ref.shape and bool(np.all((got == ref) | (np.isnan(got) & np.isnan(ref))))

@@ -1,0 +1,162 @@
+"""The C-ABI library: it loads, exports every symbol the header declares, and
+rejects invalid arguments with the documented status before touching the GPU.
+These tests make no compute call and run without a GPU."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1409_0669_amd import _lib
+    return _lib
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "bwla.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bwla_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L.lib, n), n
+    # and the binding declares a signature for each of them
+    assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
+
+
+def test_abi_version_and_strings(L):
+    assert L.lib.bwla_abi_version() == 1
+    for st, name in [(0, b"ok"), (1, b"invalid argument"), (3, b"workspace too small"), (4, b"HIP error")]:
+        assert L.lib.bwla_status_string(st) == name
+
+
+FAKE = 1 << 40  # an address that is never dereferenced: validation fails first
+
+
+def st(L, r):
+    return r, L.lib.bwla_last_error().decode()
+
+
+def test_vector_validation(L):
+    lib = L.lib
+    assert lib.bwla_copy(0, -1, FAKE, FAKE + 4096, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_copy(7, 10, FAKE, FAKE + 4096, None) == L.ERR_UNSUPPORTED
+    assert lib.bwla_copy(0, 10, None, FAKE, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_copy(0, 0, None, None, None) == L.OK          # empty: nothing to do
+    # partial overlap x = y + 1 element
+    assert lib.bwla_copy(0, 10, FAKE, FAKE + 8, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_axpby(0, 10, 1.0, None, FAKE, 1.0, None, FAKE + 8000, FAKE + 8, None) == L.ERR_INVALID_ARG
+    assert "overlap" in lib.bwla_last_error().decode()
+    assert lib.bwla_axpby(0, -5, 1.0, None, FAKE, 1.0, None, FAKE, FAKE, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_axpby(0, 5, 1.0, None, None, 1.0, None, FAKE, FAKE, None) == L.ERR_INVALID_ARG
+    # device scalar inside the output
+    assert lib.bwla_axpby(0, 10, 1.0, FAKE + 16, FAKE + 4096, 1.0, None, FAKE + 8192, FAKE, None) == L.ERR_INVALID_ARG
+
+
+def test_reduction_validation(L):
+    lib = L.lib
+    out = FAKE + (1 << 20)
+    assert lib.bwla_dot(0, 0, -1, FAKE, FAKE, 0, out, None, 0, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_dot(0, 5, 10, FAKE, FAKE, 0, out, None, 0, None) == L.ERR_UNSUPPORTED
+    assert lib.bwla_dot(0, 0, 10, FAKE, FAKE, 1, out, None, 0, None) == L.ERR_UNSUPPORTED  # f64 -> f32 out
+    assert lib.bwla_dot(1, 0, 10, FAKE, FAKE, 2, out, None, 0, None) == L.ERR_UNSUPPORTED  # bf16 out
+    assert lib.bwla_dot(0, 0, 10, FAKE, FAKE, 0, None, None, 0, None) == L.ERR_INVALID_ARG
+    # a long dot needs a workspace
+    assert lib.bwla_dot(0, 0, 1 << 24, FAKE, FAKE + (1 << 28), 0, out, None, 0, None) == L.ERR_WORKSPACE
+    assert lib.bwla_dot(0, 0, 1 << 24, FAKE, FAKE + (1 << 28), 0, out, FAKE + (1 << 30), 100, None) == L.ERR_WORKSPACE
+    # output inside an input
+    assert lib.bwla_dot(0, 0, 100, FAKE, FAKE + 4096, 0, FAKE + 64, FAKE + (1 << 30), 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_nrm2(0, 0, -3, FAKE, 0, out, None, 0, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_cg_update(0, 0, 10, 1.0, None, FAKE, FAKE, FAKE, FAKE, 0, out, FAKE + (1 << 30), 1 << 20,
+                              None) == L.ERR_INVALID_ARG  # x overlaps r
+
+
+def test_gemv_validation(L):
+    lib = L.lib
+    y = FAKE + (1 << 34)
+    x = FAKE + (1 << 33)
+    A = FAKE
+    assert lib.bwla_gemv(0, 0, 0, 0, 10, 20, A, 19, x, 0, y, None, 0, None) == L.ERR_INVALID_ARG  # lda < n
+    assert lib.bwla_gemv(0, 0, 1, 0, 10, 20, A, 9, x, 0, y, None, 0, None) == L.ERR_INVALID_ARG   # col: lda < m
+    assert lib.bwla_gemv(0, 0, 2, 0, 10, 20, A, 20, x, 0, y, None, 0, None) == L.ERR_INVALID_ARG  # layout
+    assert lib.bwla_gemv(0, 0, 0, 2, 10, 20, A, 20, x, 0, y, None, 0, None) == L.ERR_INVALID_ARG  # trans
+    assert lib.bwla_gemv(0, 0, 0, 0, -1, 20, A, 20, x, 0, y, None, 0, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv(0, 0, 0, 0, 10, 20, None, 20, x, 0, y, None, 0, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv(0, 0, 0, 0, 10, 20, A, 20, x, 0, A + 80, None, 0, None) == L.ERR_INVALID_ARG  # y in A
+    assert lib.bwla_gemv(0, 0, 0, 0, 0, 20, A, 20, x, 0, None, None, 0, None) == L.OK  # no outputs
+    assert lib.bwla_gemv(2, 0, 0, 0, 10, 20, A, 20, x, 2, y, None, 0, None) == L.ERR_UNSUPPORTED  # bf16 out
+    assert lib.bwla_ger(0, 0, 10, 20, x, x + 800, A, 19, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_ger(0, 0, 10, 20, A + 8, x, A, 20, None) == L.ERR_INVALID_ARG  # u inside A
+    assert lib.bwla_ger(0, 0, 0, 20, None, None, None, 20, None) == L.OK
+
+
+def test_workspace_sizes(L):
+    lib = L.lib
+    b = ctypes.c_size_t()
+    assert lib.bwla_workspace_size(L.OP_DOT, 0, 0, 0, 0, 0, 1 << 26, ctypes.byref(b)) == L.OK
+    assert b.value >= L.WS_COUNTER_BYTES
+    assert lib.bwla_workspace_size(L.OP_GEMV_ROWS, 0, 0, 1, 0, 16384, 16384, ctypes.byref(b)) == L.OK
+    col = b.value
+    assert col > L.WS_COUNTER_BYTES          # column-major y = A x splits across lines
+    assert lib.bwla_workspace_size(L.OP_GEMV_ROWS, 0, 0, 0, 0, 16384, 16384, ctypes.byref(b)) == L.OK
+    assert lib.bwla_workspace_size(L.OP_DOT, 0, 0, 0, 0, -1, 5, ctypes.byref(b)) == L.ERR_INVALID_ARG
+
+
+def test_config_table(L):
+    lib = L.lib
+    c = L.Config(block=512, vec=4, unroll=2, grid=1024, increment=1, rows=0, split=0)
+    assert lib.bwla_set_config(L.OP_AXPBY, 1, -1, ctypes.byref(c)) == L.OK
+    got = L.Config()
+    assert lib.bwla_get_config(L.OP_AXPBY, 1, 0, 1000, ctypes.byref(got)) == L.OK
+    assert (got.block, got.vec, got.unroll, got.grid, got.increment) == (512, 4, 2, 1024, 1)
+    assert lib.bwla_set_config(L.OP_AXPBY, 1, -1, None) == L.OK
+    assert lib.bwla_get_config(L.OP_AXPBY, 1, 0, 1000, ctypes.byref(got)) == L.OK
+    assert (got.block, got.vec) == (256, 4)
+    bad = L.Config(block=100)
+    assert lib.bwla_set_config(L.OP_COPY, 0, 0, ctypes.byref(bad)) == L.ERR_INVALID_ARG
+    bad = L.Config(vec=3)
+    assert lib.bwla_set_config(L.OP_COPY, 0, 0, ctypes.byref(bad)) == L.ERR_INVALID_ARG
+    assert lib.bwla_set_config(99, 0, 0, None) == L.ERR_INVALID_ARG
+
+
+def test_load_tuning(L, tmp_path):
+    lib = L.lib
+    p = tmp_path / "t.txt"
+    p.write_text("# op dtype class block vec unroll grid inc rows split\n"
+                 "1 0 -1 512 2 2 0 0 0 0   # axpby f64\n\n"
+                 "3 1 3 256 4 1 0 0 8 2\n")
+    assert lib.bwla_load_tuning(str(p).encode()) == L.OK
+    got = L.Config()
+    lib.bwla_get_config(L.OP_AXPBY, 0, 0, 1 << 20, ctypes.byref(got))
+    assert (got.block, got.vec, got.unroll) == (512, 2, 2)
+    lib.bwla_get_config(L.OP_GEMV_ROWS, 1, 16384, 16384, ctypes.byref(got))
+    assert (got.rows, got.split) == (8, 2)
+    p.write_text("1 0 -1 500 2 2 0 0 0 0\n")
+    assert lib.bwla_load_tuning(str(p).encode()) == L.ERR_INVALID_ARG
+    assert lib.bwla_load_tuning(b"/nonexistent/file") == L.ERR_INVALID_ARG
+    for op in range(6):
+        for t in range(3):
+            lib.bwla_set_config(op, t, -1, None)
+
+
+def test_batch_plan_validation(L):
+    lib = L.lib
+    h = ctypes.c_void_p()
+    g = (L.GemvDesc * 1)(L.GemvDesc(FAKE, 10, 20, 19, FAKE + (1 << 30), FAKE + (1 << 31)))
+    d = (L.DotDesc * 1)()
+    assert lib.bwla_batch_plan_create(0, 0, 0, g, 1, d, 0, None, ctypes.byref(h)) == L.ERR_INVALID_ARG
+    assert not h.value
+    d = (L.DotDesc * 1)(L.DotDesc(FAKE, FAKE, 10, None))
+    assert lib.bwla_batch_plan_create(0, 0, 0, g, 0, d, 1, None, ctypes.byref(h)) == L.ERR_INVALID_ARG
+    assert lib.bwla_batch_plan_create(0, 0, 1, g, 0, d, 0, None, ctypes.byref(h)) == L.ERR_UNSUPPORTED
+    assert lib.bwla_batch_run(None, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_batch_replay(None, None) == L.ERR_INVALID_ARG

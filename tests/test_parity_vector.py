@@ -1,0 +1,118 @@
+"""GPU parity of the streaming kernels: copy and scaled vector addition are
+single-rounding operations, so they must match the oracle bitwise (0 ULP in
+matching precision) for every size, alignment, aliasing and configuration."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.criteria import bitwise_equal
+from tests.gpu_util import DT, host, need_gpu, vec
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 3, 7, 63, 64, 65, 255, 1000, 4097, (1 << 20) + 3]
+DTYPES = ["f64", "f32", "bf16"]
+ALPHA, BETA = 0.7312345678901234, -1.2345678901234567
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+    from paper_1409_0669_amd import ops
+    ops.reset_config()
+    yield
+    ops.reset_config()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", SIZES)
+def test_copy_bitwise(dtype, n):
+    from paper_1409_0669_amd import ops
+    y, y64 = vec(n, dtype, 1)
+    x = ops.copy(y)
+    assert bitwise_equal(host(x), oracle.copy(y64))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", SIZES)
+def test_axpby_bitwise(dtype, n):
+    from paper_1409_0669_amd import ops
+    y, y64 = vec(n, dtype, 1)
+    z, z64 = vec(n, dtype, 2)
+    x = ops.axpby(ALPHA, y, BETA, z)
+    ref = oracle.axpby(dtype, oracle.scalar(dtype, ALPHA), y64, oracle.scalar(dtype, BETA), z64)
+    assert bitwise_equal(host(x), ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("offsets", [(1, 0, 0), (0, 1, 3), (3, 3, 3)])
+def test_axpby_misaligned(dtype, offsets):
+    from paper_1409_0669_amd import ops
+    n = 10007
+    y, y64 = vec(n, dtype, 3, pad_front=offsets[0])
+    z, z64 = vec(n, dtype, 4, pad_front=offsets[1])
+    out = torch.empty(n + offsets[2], dtype=DT[dtype], device="cuda")[offsets[2]:]
+    ops.axpby(ALPHA, y, BETA, z, out=out)
+    ref = oracle.axpby(dtype, oracle.scalar(dtype, ALPHA), y64, oracle.scalar(dtype, BETA), z64)
+    assert bitwise_equal(host(out), ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_axpby_in_place_and_device_scalars(dtype):
+    from paper_1409_0669_amd import ops
+    n = 70001
+    y, y64 = vec(n, dtype, 5)
+    z, z64 = vec(n, dtype, 6)
+    cd = ops.compute_dtype(DT[dtype])
+    a_dev = torch.tensor([0.377], dtype=cd, device="cuda")
+    b_dev = torch.tensor([-2.5], dtype=cd, device="cuda")
+    a_val, b_val = float(a_dev.item()), float(b_dev.item())
+    # x += a*p form: out aliases z
+    ops.axpby(0.9, y, 1.0, z, out=z, alpha_dev=a_dev)
+    ref = oracle.axpby(dtype, oracle.scalar(dtype, 0.9, a_val), y64, 1.0, z64)
+    assert bitwise_equal(host(z), ref)
+    # out aliases y, both factors on the device
+    ops.axpby(1.5, y, 0.25, z, out=y, alpha_dev=a_dev, beta_dev=b_dev)
+    ref2 = oracle.axpby(dtype, oracle.scalar(dtype, 1.5, a_val), y64, oracle.scalar(dtype, 0.25, b_val), ref)
+    assert bitwise_equal(host(y), ref2)
+
+
+CONFIGS = [
+    dict(block=64, vec=1, unroll=1, grid=1),
+    dict(block=128, vec=2, unroll=2, grid=3, increment=1),
+    dict(block=256, vec=4, unroll=4, grid=7),
+    dict(block=1024, vec=8, unroll=1, grid=0, increment=1),
+    dict(block=512, vec=16, unroll=2, grid=5),
+    dict(block=256, vec=16, unroll=4, grid=0),
+]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("cfg", range(len(CONFIGS)))
+def test_stream_configs_bitwise(dtype, cfg):
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    ops.set_config(L.OP_AXPBY, DT[dtype], -1, **CONFIGS[cfg])
+    ops.set_config(L.OP_COPY, DT[dtype], -1, **CONFIGS[cfg])
+    for n in (5, 4099, 300017):
+        y, y64 = vec(n, dtype, 7)
+        z, z64 = vec(n, dtype, 8)
+        x = ops.axpby(ALPHA, y, BETA, z)
+        ref = oracle.axpby(dtype, oracle.scalar(dtype, ALPHA), y64, oracle.scalar(dtype, BETA), z64)
+        assert bitwise_equal(host(x), ref), (n, CONFIGS[cfg])
+        assert bitwise_equal(host(ops.copy(y)), y64)
+
+
+def test_axpby_empty_and_specials():
+    from paper_1409_0669_amd import ops
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    assert ops.axpby(1.0, e, 1.0, e).numel() == 0
+    y = torch.tensor([1.0, float("inf"), float("nan"), -0.0, 3.0], dtype=torch.float64, device="cuda")
+    z = torch.tensor([float("inf"), 1.0, 1.0, 0.0, -3.0], dtype=torch.float64, device="cuda")
+    x = host(ops.axpby(2.0, y, 0.0, z))     # beta = 0 still reads z: 0*inf = nan
+    ref = oracle.axpby("f64", 2.0, host(y), 0.0, host(z))
+    assert bitwise_equal(x, ref)
+    assert np.isnan(x[0])

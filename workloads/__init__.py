@@ -96,6 +96,28 @@ def vector(n: int, dtype: str, seed: int = 0, stream: int = 0, dist: str = "unif
     return s, widen(s, dtype)
 
 
+def device_draw(n, dtype: str, seed: int = 0, stream: int = 0, dist: str = "uniform", device="cuda"):
+    """Seeded draws generated directly in device memory (for inputs too large
+    to draw on the host quickly): torch's Philox generator on the device,
+    seeded from SeedSequence([seed, stream]); float64 uniform on [-1, 1) or
+    standard normal, rounded to the storage type (f64 -> f32 -> bf16, nearest
+    even).  Download with :func:`from_torch` for exact float64 values."""
+    import torch
+    state = int(np.random.SeedSequence([int(seed), int(stream)]).generate_state(1, np.uint64)[0])
+    g = torch.Generator(device=device)
+    g.manual_seed(state & ((1 << 63) - 1))
+    if dist == "uniform":
+        t = torch.rand(n, generator=g, dtype=torch.float64, device=device).mul_(2.0).sub_(1.0)
+    elif dist == "normal":
+        t = torch.randn(n, generator=g, dtype=torch.float64, device=device)
+    else:
+        raise ValueError(dist)
+    if dtype == "f64":
+        return t
+    t = t.to(torch.float32)
+    return t if dtype == "f32" else t.to(torch.bfloat16)
+
+
 def loguniform_sizes(lo: int, hi: int, count: int, seed: int = 0, stream: int = 0) -> np.ndarray:
     u = rng(seed, stream).uniform(np.log(lo), np.log(hi), size=count)
     return np.clip(np.rint(np.exp(u)), lo, hi).astype(np.int64)
