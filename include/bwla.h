@@ -25,13 +25,13 @@
  *    Arithmetic is carried out in the "compute precision": double for f64
  *    storage, float for f32 and bf16 storage.  Every conversion to a narrower
  *    format rounds to nearest, ties to even.
- *  - Reductions (dot, nrm2, gemv) take a workspace `ws` of at least
- *    bwla_workspace_size() bytes.  The workspace must be zero-filled once
- *    when it is allocated; every call leaves its first BWLA_WS_COUNTER_BYTES
- *    bytes zero again when it completes, so one workspace can serve any
- *    sequence of calls on ONE stream.  Calls that may run concurrently (other
- *    streams) need separate workspaces.  No entry point allocates device
- *    memory except bwla_batch_plan_create.
+ *  - Reductions (dot, nrm2, gemv, cg_update) take a workspace `ws` of at
+ *    least bwla_workspace_size() bytes for the float64 partial sums of their
+ *    first stage; a second small kernel combines them in a fixed order.  Its
+ *    contents on entry do not matter.  One workspace serves any sequence of
+ *    calls on ONE stream; calls that may run concurrently (other streams)
+ *    need separate workspaces.  ws may be NULL when the size is 0.  No entry
+ *    point allocates device memory except bwla_batch_plan_create.
  */
 #ifndef BWLA_H
 #define BWLA_H
@@ -44,7 +44,6 @@ extern "C" {
 #endif
 
 #define BWLA_ABI_VERSION 1
-#define BWLA_WS_COUNTER_BYTES 65536
 
 typedef enum {
     BWLA_OK = 0,
@@ -121,9 +120,9 @@ bwla_status bwla_axpby(bwla_dtype t, int64_t n, double alpha, const void *alpha_
                        void *x, void *stream);
 
 /* ---- inner product: out <- <x, y> (paper Section 2, inner product) --------
- * Two-stage reduction: each work-group writes a float64 partial, and the
- * last work-group to finish (atomic ticket) combines all partials in a fixed
- * order, so the result is deterministic for a given configuration.  out is
+ * Two-stage reduction: each work-group writes a float64 partial, and a
+ * second one-work-group kernel combines all partials in a fixed order, so
+ * the result is deterministic for a given configuration.  out is
  * ONE device element of out_t: BWLA_F64 for f64 input; BWLA_F32 or BWLA_F64
  * for f32/bf16 input.  n == 0 writes 0. */
 bwla_status bwla_dot(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
@@ -178,13 +177,14 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
  * (out = <x, y>, out_t output) of one storage type.  Work is flattened into
  * items (row tiles of a GEMV, chunks of a dot) ordered largest first; a
  * persistent grid takes items from an atomic counter.  Each dot's chunk
- * partials are combined in chunk order by the last chunk to finish, so
- * results do not depend on the batch order or on scheduling.
+ * partials are combined in chunk order by a finalize kernel, so results do
+ * not depend on the batch order or on scheduling.
  * create: copies the descriptors to the device and allocates the plan's own
  *         counters and partial slots (the only allocating call; not allowed
  *         while `stream` capture is active).
- * run:    enqueues the counter reset and the persistent kernel.
- * capture: records the same two kernels into a HIP graph owned by the plan.
+ * run:    enqueues the counter reset, the persistent kernel and the dot
+ *         finalize kernel.
+ * capture: records the same three kernels into a HIP graph owned by the plan.
  * replay: launches the captured graph.
  * Descriptor pointers must stay valid while the plan is used. */
 typedef struct bwla_batch_plan bwla_batch_plan;

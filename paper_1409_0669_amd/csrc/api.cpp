@@ -165,7 +165,7 @@ Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
     c.grid = 0;
     c.inc = 0;
     c.rows = u.rows ? u.rows : 4;
-    const int64_t groups = ceil_div(L, c.rows);
+    const int64_t groups = std::max<int64_t>(1, ceil_div(L, c.rows));
     int64_t split = u.split;
     if (!split) {
         const int64_t target = (int64_t)device_cus() * 8;
@@ -173,8 +173,6 @@ Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
         split = groups >= target / 2 ? 1 : ceil_div(target, groups);
         split = std::min<int64_t>(split, std::max<int64_t>(1, kpack / (2 * c.block)));
     }
-    if (groups > kMaxCounters)
-        split = 1;
     split = std::max<int64_t>(1, std::min<int64_t>(split, std::max<int64_t>(1, K)));
     split = std::min<int64_t>(split, (int64_t)(0x7fffffff / std::max<int64_t>(1, groups)));
     c.split = (int)split;
@@ -191,7 +189,7 @@ Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
     c.grid = 0;
     c.inc = 0;
     c.rows = 1;
-    const int64_t tiles = ceil_div(K, 64 * (int64_t)c.vec);
+    const int64_t tiles = std::max<int64_t>(1, ceil_div(K, 64 * (int64_t)c.vec));
     int64_t split = u.split;
     if (!split) {
         const int64_t target = (int64_t)device_cus() * 8;
@@ -199,8 +197,6 @@ Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
         split = tiles >= target ? 1 : ceil_div(target, tiles);
         split = std::min<int64_t>(split, std::max<int64_t>(1, L / (waves * 16)));
     }
-    if (tiles > kMaxCounters)
-        split = 1;
     split = std::max<int64_t>(1, std::min<int64_t>(split, std::max<int64_t>(1, L)));
     split = std::min<int64_t>(split, (int64_t)(0x7fffffff / std::max<int64_t>(1, tiles)));
     c.split = (int)split;
@@ -222,18 +218,19 @@ Cfg resolve_ger(int t, int64_t L, int64_t K, const void *a, const void *b, const
     return c;
 }
 
-size_t ws_dot(const Cfg &c) { return kCounterBytes + (size_t)c.grid * sizeof(DD); }
+// Workspace = the float64 (DD) partials of the first stage.
+size_t ws_dot(const Cfg &c) { return c.grid > 1 ? (size_t)c.grid * sizeof(DD) : 0; }
 size_t ws_rows(const Cfg &c, int64_t L)
 {
     if (c.split <= 1)
         return 0;
-    return kCounterBytes + (size_t)ceil_div(L, c.rows) * c.split * c.rows * sizeof(DD);
+    return (size_t)ceil_div(L, c.rows) * c.split * c.rows * sizeof(DD);
 }
 size_t ws_cols(const Cfg &c, int64_t K)
 {
     if (c.split <= 1)
         return 0;
-    return kCounterBytes + (size_t)ceil_div(K, 64 * (int64_t)c.vec) * c.split * 64 * c.vec * sizeof(DD);
+    return (size_t)ceil_div(K, 64 * (int64_t)c.vec) * c.split * 64 * c.vec * sizeof(DD);
 }
 
 // --- overlap checks ----------------------------------------------------------
@@ -368,7 +365,7 @@ static bwla_status dot_common(bwla_dtype t, bwla_acc acc, int64_t n, const void 
                               void *stream)
 {
     Cfg c = resolve_vector(BWLA_OP_DOT, t, n, {x, y}, square ? 1 : 2);
-    const size_t need = n > 0 && c.grid > 1 ? ws_dot(c) : 0;
+    const size_t need = n > 0 ? ws_dot(c) : 0;
     bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
     if (st)
         return st;
@@ -513,8 +510,8 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha, 
                            void *x, const void *p, void *r, const void *q, bwla_dtype out_t, void *out,
                            void *ws, size_t ws_bytes, void *stream)
 {
-    Cfg c = resolve_vector(BWLA_OP_DOT, t, n, {x, p, r, q}, 6);
-    const size_t need = n > 0 && c.grid > 1 ? ws_dot(c) : 0;
+    Cfg c = resolve_vector(BWLA_OP_DOT, t, n, {x, p, r, q}, 2);
+    const size_t need = n > 0 ? ws_dot(c) : 0;
     bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
     if (st)
         return st;
@@ -564,6 +561,8 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
             if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
                 return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
             GemvPlan g = gemv_plan(layout, trans, m, n);
+            if (g.out_len == 0 || g.in_len == 0)
+                break; // no kernel runs
             if (g.rows)
                 best = std::max(best, ws_rows(resolve_rows(t, g.L, g.K, fake, v, fake), g.L));
             else
@@ -686,7 +685,7 @@ struct bwla_batch_plan {
     BatchGemv *d_gemv = nullptr;
     BatchDot *d_dots = nullptr;
     double *d_partials = nullptr;
-    unsigned *d_counters = nullptr; // [0] = work counter, [1..] = per-dot tickets
+    unsigned *d_counters = nullptr; // the work counter
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -710,7 +709,7 @@ void plan_free(bwla_batch_plan *p)
 
 hipError_t enqueue_batch(bwla_batch_plan *p, hipStream_t s)
 {
-    hipError_t e = launch_batch_reset(p->d_counters, 1 + p->n_dots, s);
+    hipError_t e = launch_batch_reset(p->d_counters, 1, s);
     if (e != hipSuccess)
         return e;
     BatchArgs a;
@@ -719,14 +718,17 @@ hipError_t enqueue_batch(bwla_batch_plan *p, hipStream_t s)
     a.gemv = p->d_gemv;
     a.dots = p->d_dots;
     a.partials = p->d_partials;
-    a.dot_counters = p->d_counters + 1;
     a.work_counter = p->d_counters;
     a.out_f64 = p->out_t == BWLA_F64;
     a.vec = p->vec;
-    return by_type(p->t, [&](auto *tag) {
+    e = by_type(p->t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         return launch_batched<T>(a, p->acc == BWLA_ACC_COMPENSATED, p->grid, p->block, s);
     });
+    if (e != hipSuccess)
+        return e;
+    return launch_batch_finalize(p->d_dots, p->n_dots, p->d_partials, p->acc == BWLA_ACC_COMPENSATED,
+                                 p->out_t == BWLA_F64, s);
 }
 } // namespace
 
@@ -882,7 +884,7 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
     if (e == hipSuccess)
         e = alloc_copy((void **)&p->d_partials, nullptr, (size_t)std::max<int64_t>(1, slots) * 2 * sizeof(double));
     if (e == hipSuccess) {
-        std::vector<unsigned> zeros((size_t)(1 + nd), 0u);
+        std::vector<unsigned> zeros(1, 0u);
         e = alloc_copy((void **)&p->d_counters, zeros.data(), zeros.size() * sizeof(unsigned));
     }
     if (e != hipSuccess) {

@@ -6,11 +6,11 @@
 // takes the next item from an atomic counter until the list is exhausted, so
 // every wave reaches the exit.  GEMV rows are handled by groups of G lanes
 // (G a power of two sized to the row length), reduced by butterfly exchanges
-// inside the group.  A dot chunk is reduced by the whole work-group; its
-// float64 partial goes to a slot of the dot, and the last chunk to finish
-// (atomic ticket) combines the dot's slots in chunk order.  Every result
-// depends only on its own problem's sizes, never on the batch order or on
-// which work-group ran which item.
+// inside the group.  A dot chunk is reduced by the whole work-group; a
+// single-chunk dot writes its result directly, otherwise the chunk's float64
+// partial goes to a slot of the dot and a small finalize kernel combines each
+// dot's slots in chunk order.  Every result depends only on its own problem's
+// sizes, never on the batch order or on which work-group ran which item.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -50,7 +50,7 @@ __device__ __forceinline__ void gemv_tile(const BatchGemv &g, int64_t rb, int64_
 }
 
 template <typename T, int V, bool COMP>
-__device__ __forceinline__ void dot_chunk(const BatchArgs &a, const BatchItem &w, DD *lds, int *flag)
+__device__ __forceinline__ void dot_chunk(const BatchArgs &a, const BatchItem &w, DD *lds)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -84,17 +84,8 @@ __device__ __forceinline__ void dot_chunk(const BatchArgs &a, const BatchItem &w
             store_out(d.out, 0, a.out_f64, v.hi + v.lo);
         return;
     }
-    DD *slots = reinterpret_cast<DD *>(a.partials) + d.slot0;
     if (threadIdx.x == 0)
-        slots[w.chunk] = v;
-    if (last_arrival(&a.dot_counters[w.prob], (unsigned)d.chunks, flag)) {
-        if (threadIdx.x == 0) {
-            DD t = slots[0];
-            for (int c = 1; c < d.chunks; ++c)
-                t = combine<COMP>(t, slots[c]);
-            store_out(d.out, 0, a.out_f64, t.hi + t.lo);
-        }
-    }
+        reinterpret_cast<DD *>(a.partials)[d.slot0 + w.chunk] = v;
 }
 
 template <typename T, int V, bool COMP>
@@ -102,7 +93,6 @@ __global__ __launch_bounds__(1024) void k_batched(BatchArgs a)
 {
     __shared__ unsigned next;
     __shared__ DD lds[16];
-    __shared__ int flag;
     for (;;) {
         if (threadIdx.x == 0)
             next = atomicAdd(a.work_counter, 1u);
@@ -115,7 +105,7 @@ __global__ __launch_bounds__(1024) void k_batched(BatchArgs a)
         if (w.kind == 0)
             gemv_tile<T, V, COMP>(a.gemv[w.prob], w.begin, w.end, a.out_f64);
         else
-            dot_chunk<T, V, COMP>(a, w, lds, &flag);
+            dot_chunk<T, V, COMP>(a, w, lds);
     }
 }
 
@@ -125,6 +115,25 @@ __global__ void k_zero_counters(unsigned *c, int64_t count)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
         c[i] = 0u;
+}
+
+// One thread per dot: combine the chunk partials of multi-chunk dots in
+// chunk order (single-chunk dots were written by the batched kernel).
+template <bool COMP>
+__global__ __launch_bounds__(256) void k_batch_finalize(const BatchDot *dots, int64_t nd, const DD *partials,
+                                                        int out_f64)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd)
+        return;
+    const BatchDot d = dots[i];
+    if (d.chunks <= 1)
+        return;
+    const DD *p = partials + d.slot0;
+    DD t = p[0];
+    for (int c = 1; c < d.chunks; ++c)
+        t = combine<COMP>(t, p[c]);
+    store_out(d.out, 0, out_f64, t.hi + t.lo);
 }
 #endif
 
@@ -155,6 +164,19 @@ hipError_t launch_batch_reset(unsigned *counters, int64_t count, hipStream_t s)
         blocks = 1;
     hipLaunchKernelGGL(k_zero_counters, dim3((unsigned)blocks), dim3(256), 0, s, counters, count);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchDot *dots, int64_t nd, const double *partials, bool comp,
+                                 int out_f64, hipStream_t s)
+{
+    if (nd <= 0)
+        return hipSuccess;
+    const int64_t blocks = (nd + 255) / 256;
+    return with_bool(comp, [&](auto CP) {
+        hipLaunchKernelGGL((k_batch_finalize<CP.value>), dim3((unsigned)blocks), dim3(256), 0, s, dots, nd,
+                           (const DD *)partials, out_f64);
+        return hipGetLastError();
+    });
 }
 #endif
 

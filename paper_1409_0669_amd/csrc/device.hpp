@@ -1,7 +1,12 @@
 // device.hpp -- gfx950 device building blocks shared by the library's kernels:
 // storage/compute type traits, 16-byte packed global loads and stores,
-// error-free transformations, wave64 and work-group float64 reductions, and
-// the last-work-group ticket used by every two-stage reduction.
+// error-free transformations, and wave64 and work-group float64 reductions.
+//
+// Cross-work-group combines are done by a second, small kernel rather than by
+// a "last work-group" ticket inside the first: on gfx950 every agent-scope
+// fence that such a ticket needs writes back and invalidates the XCD's L2,
+// which serialises badly across thousands of work-groups.  The kernel
+// boundary gives the visibility for free and keeps the combine order fixed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -243,32 +248,6 @@ template <bool COMP> __device__ __forceinline__ DD block_sum(DD v, DD *lds)
     t = wave_sum<COMP>(t);
     __syncthreads(); // lds may be reused by the caller afterwards
     return t;
-}
-
-// ---------------------------------------------------------------------------
-// Last-work-group ticket.  Each participant publishes its partials, every
-// thread fences (agent-scope release), then one thread takes a ticket; the
-// participant that draws the last ticket fences again (acquire) in every
-// thread, so it sees every partial, and resets the counter for the next call.
-// Must be called by every thread of the block; returns true in every thread
-// of the last block.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool last_arrival(unsigned *counter, unsigned participants, int *lds_flag)
-{
-    __threadfence(); // release this thread's partial stores at agent scope
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(counter, 1u);
-        int last = (t == participants - 1);
-        if (last)
-            atomicExch(counter, 0u);
-        *lds_flag = last;
-    }
-    __syncthreads();
-    bool last = *lds_flag != 0;
-    if (last)
-        __threadfence();
-    return last;
 }
 
 // Rounds a float64 result to the output element type.

@@ -12,8 +12,8 @@
 //   thread loads a pack of v once into registers and reuses it for the R
 //   lines, so v is read from cache once per R lines of A.  The R sums are
 //   reduced across the wave (DPP) and across waves through LDS.  With split >
-//   1 the slices' float64 partials are combined in slice order by the last
-//   work-group of the line group to finish.
+//   1 each slice writes float64 partials and a second kernel combines them in
+//   slice order.
 //
 // cols kernel: out[k] = sum_l A[l*ld + k] v[l].  A work-group owns a tile of
 //   64*V consecutive outputs (V per lane, so each wave access is 64*V
@@ -21,8 +21,8 @@
 //   take interleaved lines of the slice, U lines in flight.  The slice of v is
 //   staged in LDS (converted to the compute precision) and read as a
 //   wave-uniform broadcast.  Per-wave partial sums are combined through LDS in
-//   wave order; slices are combined in slice order by the last work-group of
-//   the tile.
+//   wave order; with split > 1 the slices' partials are combined in slice
+//   order by a second kernel.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -30,8 +30,8 @@ namespace bwla {
 
 template <typename T, int V, int R, bool COMP>
 __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const T *A, int64_t ld,
-                                                    const T *v, DD *partials, unsigned *counters,
-                                                    void *out, int out_f64, int split)
+                                                    const T *v, DD *partials, void *out, int out_f64,
+                                                    int split)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -72,7 +72,6 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
     }
 
     __shared__ DD lds[16 * R];
-    __shared__ int flag;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -81,33 +80,23 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
             lds[wave * R + r] = d;
     }
     __syncthreads();
-    DD t = {0.0, 0.0};
     if (threadIdx.x < R) {
-        t = lds[threadIdx.x];
+        DD t = lds[threadIdx.x];
         for (int w = 1; w < nw; ++w)
             t = combine<COMP>(t, lds[w * R + threadIdx.x]);
-    }
-    if (split == 1) {
-        if (threadIdx.x < nr)
-            store_out(out, l0 + threadIdx.x, out_f64, t.hi + t.lo);
-        return;
-    }
-    if (threadIdx.x < R)
-        partials[(group * split + s) * R + threadIdx.x] = t;
-    if (last_arrival(&counters[group], split, &flag)) {
-        if (threadIdx.x < nr) {
-            DD u = partials[(group * split) * R + threadIdx.x];
-            for (int q = 1; q < split; ++q)
-                u = combine<COMP>(u, partials[(group * split + q) * R + threadIdx.x]);
-            store_out(out, l0 + threadIdx.x, out_f64, u.hi + u.lo);
+        if (split == 1) {
+            if (threadIdx.x < nr)
+                store_out(out, l0 + threadIdx.x, out_f64, t.hi + t.lo);
+        } else {
+            partials[(group * split + s) * R + threadIdx.x] = t;
         }
     }
 }
 
 template <typename T, int V, int U, bool COMP>
 __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const T *A, int64_t ld,
-                                                    const T *v, DD *partials, unsigned *counters,
-                                                    void *out, int out_f64, int split)
+                                                    const T *v, DD *partials, void *out, int out_f64,
+                                                    int split)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -126,7 +115,6 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
     constexpr int kStageBytes = kColsStageLines * (int)sizeof(C);
     constexpr int kRedBytes = TK * (int)sizeof(DD);
     __shared__ __attribute__((aligned(16))) char smem[kStageBytes > kRedBytes ? kStageBytes : kRedBytes];
-    __shared__ int flag;
     C *vs = reinterpret_cast<C *>(smem);
     Acc<C, COMP> acc[V];
 
@@ -189,51 +177,69 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
                 d[e] = combine<COMP>(d[e], red[lane * V + e]);
         __syncthreads();
     }
-    if (split == 1) {
-        if (wave == 0)
+    if (wave == 0) {
 #pragma unroll
-            for (int e = 0; e < V; ++e)
+        for (int e = 0; e < V; ++e) {
+            if (split == 1) {
                 if (k0 + e < K)
                     store_out(out, k0 + e, out_f64, d[e].hi + d[e].lo);
-        return;
-    }
-    if (wave == 0)
-#pragma unroll
-        for (int e = 0; e < V; ++e)
-            partials[(tile * split + s) * TK + lane * V + e] = d[e];
-    if (last_arrival(&counters[tile], split, &flag)) {
-        if (wave == 0) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                DD u = partials[(tile * split) * TK + lane * V + e];
-                for (int q = 1; q < split; ++q)
-                    u = combine<COMP>(u, partials[(tile * split + q) * TK + lane * V + e]);
-                if (k0 + e < K)
-                    store_out(out, k0 + e, out_f64, u.hi + u.lo);
+            } else {
+                partials[(tile * split + s) * TK + lane * V + e] = d[e];
             }
         }
     }
 }
+
+#if BWLA_T_IS_F64 // type-independent kernels live in the f64 object only
+// Second stage of a split GEMV: one thread per output sums its slices' float64
+// partials in slice order.  Consecutive outputs read consecutive partials.
+template <bool COMP>
+__global__ __launch_bounds__(256) void k_combine_lines(const DD *partials, int64_t outputs, int64_t G,
+                                                       int64_t split, void *out, int out_f64)
+{
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= outputs)
+        return;
+    const int64_t g = o / G, r = o - g * G;
+    const DD *p = partials + g * split * G + r;
+    DD t = p[0];
+    for (int64_t q = 1; q < split; ++q)
+        t = combine<COMP>(t, p[q * G]);
+    store_out(out, o, out_f64, t.hi + t.lo);
+}
+
+hipError_t launch_combine_lines(const void *partials, int64_t outputs, int64_t G, int64_t split,
+                                bool comp, int out_f64, void *out, hipStream_t s)
+{
+    const int64_t blocks = (outputs + 255) / 256;
+    return with_bool(comp, [&](auto CP) {
+        hipLaunchKernelGGL((k_combine_lines<CP.value>), dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const DD *)partials, outputs, G, split, out, out_f64);
+        return hipGetLastError();
+    });
+}
+#endif
 
 template <typename T>
 hipError_t launch_gemv_rows(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
                             const void *v, int out_f64, void *out, void *ws, const Cfg &c,
                             hipStream_t s)
 {
-    unsigned *counters = (unsigned *)ws;
-    DD *partials = ws ? (DD *)((char *)ws + kCounterBytes) : nullptr;
-    return with_vec(c.vec, [&](auto V) {
+    DD *partials = (DD *)ws;
+    hipError_t e = with_vec(c.vec, [&](auto V) {
         return with_rows(c.rows, [&](auto R) {
             return with_bool(comp, [&](auto CP) {
                 const int64_t groups = (L + R.value - 1) / R.value;
                 hipLaunchKernelGGL((k_gemv_rows<T, V.value, R.value, CP.value>),
                                    dim3((unsigned)(groups * c.split)), dim3(c.block), 0, s, L, K,
-                                   (const T *)A, ld, (const T *)v, partials, counters, out, out_f64,
-                                   c.split);
+                                   (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split);
                 return hipGetLastError();
             });
         });
     });
+    if (e != hipSuccess || c.split == 1)
+        return e;
+    return launch_combine_lines(partials, L, c.rows, c.split, comp, out_f64, out, s);
 }
 
 template <typename T>
@@ -241,20 +247,21 @@ hipError_t launch_gemv_cols(int64_t L, int64_t K, bool comp, const void *A, int6
                             const void *v, int out_f64, void *out, void *ws, const Cfg &c,
                             hipStream_t s)
 {
-    unsigned *counters = (unsigned *)ws;
-    DD *partials = ws ? (DD *)((char *)ws + kCounterBytes) : nullptr;
-    return with_vec(c.vec, [&](auto V) {
+    DD *partials = (DD *)ws;
+    hipError_t e = with_vec(c.vec, [&](auto V) {
         return with_unroll(c.unroll, [&](auto U) {
             return with_bool(comp, [&](auto CP) {
                 const int64_t tiles = (K + 64 * V.value - 1) / (64 * V.value);
                 hipLaunchKernelGGL((k_gemv_cols<T, V.value, U.value, CP.value>),
                                    dim3((unsigned)(tiles * c.split)), dim3(c.block), 0, s, L, K,
-                                   (const T *)A, ld, (const T *)v, partials, counters, out, out_f64,
-                                   c.split);
+                                   (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split);
                 return hipGetLastError();
             });
         });
     });
+    if (e != hipSuccess || c.split == 1)
+        return e;
+    return launch_combine_lines(partials, K, 64 * (int64_t)c.vec, c.split, comp, out_f64, out, s);
 }
 
 template hipError_t launch_gemv_rows<BWLA_T>(int64_t, int64_t, bool, const void *, int64_t,

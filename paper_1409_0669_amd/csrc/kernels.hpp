@@ -14,10 +14,7 @@ struct Cfg {
     int block, vec, unroll, grid, inc, rows, split;
 };
 
-// Workspace layout of the reductions: a fixed counter region first (left
-// zero by every call), float64 partials after it.
-constexpr size_t kCounterBytes = 65536;
-constexpr int64_t kMaxCounters = (int64_t)(kCounterBytes / sizeof(unsigned));
+// The workspace of a reduction holds its float64 partials (DD pairs).
 constexpr int kColsStageLines = 2048; // x entries staged in LDS per pass (cols kernel)
 
 // Map a runtime value onto a compile-time constant for template dispatch.
@@ -95,6 +92,15 @@ hipError_t launch_ger(int64_t L, int64_t K, const void *a, const void *b, void *
 // --- zero fill of `count` outputs of float64 or float32 ---------------------
 hipError_t launch_fill_zero(void *out, int64_t count, int out_f64, hipStream_t s);
 
+// --- second stage of the reductions (type independent) ----------------------
+// out = sum of `count` DD partials in index order (sqrt applied if asked).
+hipError_t launch_combine_scalar(const void *partials, int64_t count, bool comp, bool do_sqrt,
+                                 int out_f64, void *out, hipStream_t s);
+// out[o] = sum over q < split of partials[((o / G) * split + q) * G + o % G],
+// for o < outputs: the slices of a split GEMV combined in slice order.
+hipError_t launch_combine_lines(const void *partials, int64_t outputs, int64_t G, int64_t split,
+                                bool comp, int out_f64, void *out, hipStream_t s);
+
 // --- batched persistent kernel ----------------------------------------------
 struct BatchItem {
     int32_t kind;   // 0 = GEMV row tile, 1 = dot chunk
@@ -126,7 +132,6 @@ struct BatchArgs {
     const BatchGemv *gemv;
     const BatchDot *dots;
     double *partials;       // 2 doubles per dot chunk
-    unsigned *dot_counters; // one per dot
     unsigned *work_counter; // next item to take
     int out_f64;
     int vec;                // elements per pack: 1 or 16 bytes' worth
@@ -134,5 +139,8 @@ struct BatchArgs {
 template <typename T>
 hipError_t launch_batched(const BatchArgs &a, bool comp, int grid, int block, hipStream_t s);
 hipError_t launch_batch_reset(unsigned *counters, int64_t count, hipStream_t s);
+// Combines the chunk partials of every multi-chunk dot, in chunk order.
+hipError_t launch_batch_finalize(const BatchDot *dots, int64_t nd, const double *partials, bool comp,
+                                 int out_f64, hipStream_t s);
 
 } // namespace bwla

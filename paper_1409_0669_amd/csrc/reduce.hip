@@ -6,10 +6,9 @@
 // compute precision, plain or compensated.  The accumulators leave the thread
 // as float64 (pairs when compensated), are summed across the wave with DPP and
 // cross-row exchanges, across the work-group through LDS, and the work-group
-// partial is written to the workspace.  Stage 2: the last work-group to finish
-// (atomic ticket) sums all partials in index order and writes the scalar.  No
-// floating-point atomics are used, so the result is deterministic for a given
-// configuration.
+// partial is written to the workspace.  Stage 2 (a one-work-group kernel)
+// sums all partials in a fixed order and writes the scalar.  No atomics are
+// used, so the result is deterministic for a given configuration.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -17,7 +16,7 @@ namespace bwla {
 
 template <typename T, int V, int U, bool COMP, bool SQ>
 __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y, DD *partials,
-                                              unsigned *counter, void *out, int out_f64, int inc)
+                                              void *out, int out_f64, int inc)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -77,25 +76,13 @@ __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y,
         v = combine<COMP>(v, acc[u].to_dd());
 
     __shared__ DD lds[16];
-    __shared__ int flag;
     DD bs = block_sum<COMP>(v, lds);
-    if (gridDim.x == 1) {
-        if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
+        if (gridDim.x == 1) {
             double r = bs.hi + bs.lo;
             store_out(out, 0, out_f64, SQ ? __builtin_sqrt(r) : r);
-        }
-        return;
-    }
-    if (threadIdx.x == 0)
-        partials[blockIdx.x] = bs;
-    if (last_arrival(counter, gridDim.x, &flag)) {
-        DD t = {0.0, 0.0};
-        for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x)
-            t = combine<COMP>(t, partials[k]);
-        t = block_sum<COMP>(t, lds);
-        if (threadIdx.x == 0) {
-            double r = t.hi + t.lo;
-            store_out(out, 0, out_f64, SQ ? __builtin_sqrt(r) : r);
+        } else {
+            partials[blockIdx.x] = bs;
         }
     }
 }
@@ -107,26 +94,45 @@ __global__ void k_fill_zero(void *out, int64_t count, int out_f64)
     for (; i < count; i += (int64_t)gridDim.x * blockDim.x)
         store_out(out, i, out_f64, 0.0);
 }
+
+// Stage 2 of the scalar reductions: one work-group sums the partials, each
+// thread a fixed strided subset, then the work-group tree.
+template <bool COMP>
+__global__ __launch_bounds__(256) void k_combine_scalar(const DD *partials, int64_t count, void *out,
+                                                        int out_f64, int do_sqrt)
+{
+    __shared__ DD lds[16];
+    DD t = {0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x)
+        t = combine<COMP>(t, partials[i]);
+    t = block_sum<COMP>(t, lds);
+    if (threadIdx.x == 0) {
+        double r = t.hi + t.lo;
+        store_out(out, 0, out_f64, do_sqrt ? __builtin_sqrt(r) : r);
+    }
+}
 #endif
 
 template <typename T>
 hipError_t launch_dot(int64_t n, bool comp, bool square, const void *x, const void *y, int out_f64,
                       void *out, void *ws, const Cfg &c, hipStream_t s)
 {
-    unsigned *counter = (unsigned *)ws;
-    DD *partials = (DD *)((char *)ws + kCounterBytes);
-    return with_vec(c.vec, [&](auto V) {
+    DD *partials = (DD *)ws;
+    hipError_t e = with_vec(c.vec, [&](auto V) {
         return with_unroll(c.unroll, [&](auto U) {
             return with_bool(comp, [&](auto CP) {
                 return with_bool(square, [&](auto SQ) {
                     hipLaunchKernelGGL((k_dot<T, V.value, U.value, CP.value, SQ.value>), dim3(c.grid),
                                        dim3(c.block), 0, s, n, (const T *)x, (const T *)y, partials,
-                                       counter, out, out_f64, c.inc);
+                                       out, out_f64, c.inc);
                     return hipGetLastError();
                 });
             });
         });
     });
+    if (e != hipSuccess || c.grid == 1)
+        return e;
+    return launch_combine_scalar(partials, c.grid, comp, square, out_f64, out, s);
 }
 
 template hipError_t launch_dot<BWLA_T>(int64_t, bool, bool, const void *, const void *, int, void *,
@@ -142,6 +148,16 @@ hipError_t launch_fill_zero(void *out, int64_t count, int out_f64, hipStream_t s
         blocks = 1;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, out, count, out_f64);
     return hipGetLastError();
+}
+
+hipError_t launch_combine_scalar(const void *partials, int64_t count, bool comp, bool do_sqrt,
+                                 int out_f64, void *out, hipStream_t s)
+{
+    return with_bool(comp, [&](auto CP) {
+        hipLaunchKernelGGL((k_combine_scalar<CP.value>), dim3(1), dim3(256), 0, s, (const DD *)partials,
+                           count, out, out_f64, (int)do_sqrt);
+        return hipGetLastError();
+    });
 }
 #endif
 

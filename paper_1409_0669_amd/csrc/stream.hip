@@ -121,8 +121,8 @@ __global__ __launch_bounds__(1024) void k_axpby(int64_t n, compute_t<T> a, const
 // ---------------------------------------------------------------------------
 template <typename T, int V, int U, bool COMP>
 __global__ __launch_bounds__(1024) void k_cg(int64_t n, compute_t<T> a, const compute_t<T> *adev, T *x,
-                                             const T *p, T *r, const T *q, DD *partials,
-                                             unsigned *counter, void *out, int out_f64, int inc)
+                                             const T *p, T *r, const T *q, DD *partials, void *out,
+                                             int out_f64, int inc)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -185,22 +185,12 @@ __global__ __launch_bounds__(1024) void k_cg(int64_t n, compute_t<T> a, const co
     for (int u = 1; u < U; ++u)
         v = combine<COMP>(v, acc[u].to_dd());
     __shared__ DD lds[16];
-    __shared__ int flag;
     DD bs = block_sum<COMP>(v, lds);
-    if (gridDim.x == 1) {
-        if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+        if (gridDim.x == 1)
             store_out(out, 0, out_f64, bs.hi + bs.lo);
-        return;
-    }
-    if (threadIdx.x == 0)
-        partials[blockIdx.x] = bs;
-    if (last_arrival(counter, gridDim.x, &flag)) {
-        DD t = {0.0, 0.0};
-        for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x)
-            t = combine<COMP>(t, partials[k]);
-        t = block_sum<COMP>(t, lds);
-        if (threadIdx.x == 0)
-            store_out(out, 0, out_f64, t.hi + t.lo);
+        else
+            partials[blockIdx.x] = bs;
     }
 }
 
@@ -240,18 +230,20 @@ hipError_t launch_cg(int64_t n, bool comp, double alpha, const void *adev, void 
                      hipStream_t s)
 {
     using C = compute_t<T>;
-    unsigned *counter = (unsigned *)ws;
-    DD *partials = (DD *)((char *)ws + kCounterBytes);
-    return with_vec(c.vec, [&](auto V) {
+    DD *partials = (DD *)ws;
+    hipError_t e = with_vec(c.vec, [&](auto V) {
         return with_unroll(c.unroll, [&](auto U) {
             return with_bool(comp, [&](auto CP) {
                 hipLaunchKernelGGL((k_cg<T, V.value, U.value, CP.value>), dim3(c.grid), dim3(c.block),
                                    0, s, n, (C)alpha, (const C *)adev, (T *)x, (const T *)p, (T *)r,
-                                   (const T *)q, partials, counter, out, out_f64, c.inc);
+                                   (const T *)q, partials, out, out_f64, c.inc);
                 return hipGetLastError();
             });
         });
     });
+    if (e != hipSuccess || c.grid == 1)
+        return e;
+    return launch_combine_scalar(partials, c.grid, comp, false, out_f64, out, s);
 }
 
 template hipError_t launch_copy<BWLA_T>(int64_t, const void *, void *, const Cfg &, hipStream_t);

@@ -59,16 +59,15 @@ def _same(dtype, device, *ts) -> None:
 
 
 # ---------------------------------------------------------------------------
-# workspace: one zero-initialised buffer per (device, stream), grown on demand
+# workspace: one buffer per (device, stream), grown on demand
 # ---------------------------------------------------------------------------
 _ws_lock = threading.Lock()
 _ws: dict = {}
 
 
 def workspace(nbytes: int, device: torch.device) -> torch.Tensor | None:
-    """A zero-filled workspace of at least ``nbytes`` for the current stream.
-    The library leaves its counter region zero after each call, so the buffer
-    is reused; it is reallocated (zero-filled) only when it must grow.  Grow it
+    """A workspace of at least ``nbytes`` for the current stream, reused by
+    every call on that stream and reallocated only when it must grow.  Grow it
     before any graph capture with :func:`reserve_workspace`."""
     if nbytes == 0:
         return None
@@ -76,9 +75,9 @@ def workspace(nbytes: int, device: torch.device) -> torch.Tensor | None:
     with _ws_lock:
         buf = _ws.get(key)
         if buf is None or buf.numel() < nbytes:
-            size = max(nbytes, L.WS_COUNTER_BYTES + (1 << 20))
+            size = max(nbytes, 1 << 20)
             size = (size + (1 << 20) - 1) >> 20 << 20
-            buf = torch.zeros(size, dtype=torch.uint8, device=device)
+            buf = torch.empty(size, dtype=torch.uint8, device=device)
             _ws[key] = buf
         return buf
 

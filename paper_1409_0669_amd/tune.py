@@ -1,0 +1,183 @@
+"""Autotuner and configuration-space study.
+
+The paper (Section 2) defines a kernel configuration as the triple of
+parameterised source, local work size and global work size, and sweeps four
+axes: loop increment (global or local), vector type (double .. double16), local
+work size (powers of two 1 .. 512) and number of work-groups (19 values) --
+2 x 5 x 10 x 19 = 1900 configurations.  Its central claim (Section 3.2 and
+Section 3.4, Table 2) is that configurations fast for the vector copy are fast
+for the other bandwidth-bound operations, so one tuned configuration serves
+them all.
+
+This module re-derives that space for gfx950 (wave64, 256 CUs; work-group sizes
+below 64 leave SIMD lanes idle, so local sizes run 64 .. 1024; the number of
+work-groups is counted per CU; an "unroll" axis gives independent accesses in
+flight), times every candidate with HIP events on the current stream, writes a
+tuning table the C library loads (``bwla_load_tuning``), and reports the copy
+proxy: each operation run with the copy's best configuration against its own
+best (the Table 2 analogue).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import statistics
+import time
+
+import torch
+
+from . import _lib as L
+from . import ops
+
+# ---- the paper's configuration space (Section 2) ---------------------------
+PAPER_INCREMENTS = ("global", "local")
+PAPER_VECTOR_TYPES = (1, 2, 4, 8, 16)
+PAPER_LOCAL_SIZES = tuple(2 ** k for k in range(10))                     # 1 .. 512
+PAPER_GROUPS = tuple(sorted(set(2 ** k for k in range(11)) | {48, 80, 96, 112, 160, 192, 224, 384}))
+
+
+def paper_space():
+    """All configurations of the paper's study, as dicts."""
+    return [dict(increment=i, vector=v, local=l, groups=g)
+            for i, v, l, g in itertools.product(PAPER_INCREMENTS, PAPER_VECTOR_TYPES,
+                                                PAPER_LOCAL_SIZES, PAPER_GROUPS)]
+
+
+# ---- the gfx950 space ------------------------------------------------------
+BLOCKS = (64, 128, 256, 512, 1024)
+VECS = (1, 2, 4, 8, 16)
+UNROLLS = (1, 2, 4)
+INCREMENTS = (L.INC_GLOBAL, L.INC_LOCAL)
+GRID_PER_CU = (1, 2, 4, 8, 16, 32, 0)   # 0 = one pass: every thread does exactly `unroll` packs
+ROWS = (1, 2, 4, 8)
+SPLITS = (0, 1, 2, 4, 8, 16, 32)          # 0 = library heuristic
+
+
+def vector_space(cus: int):
+    """Candidate configurations of the streaming and reduction kernels."""
+    out = []
+    for b, v, u, inc, g in itertools.product(BLOCKS, VECS, UNROLLS, INCREMENTS, GRID_PER_CU):
+        out.append(dict(block=b, vec=v, unroll=u, increment=inc, grid=g * cus))
+    return out
+
+
+def rows_space():
+    return [dict(block=b, vec=v, rows=r, split=s)
+            for b, v, r, s in itertools.product((64, 128, 256, 512, 1024), VECS, ROWS, SPLITS)]
+
+
+def cols_space():
+    return [dict(block=b, vec=v, unroll=u, split=s)
+            for b, v, u, s in itertools.product((64, 128, 256, 512, 1024), VECS, UNROLLS, SPLITS)]
+
+
+def size_class(nbytes: float) -> int:
+    """Size class of the library's configuration table (bytes streamed)."""
+    if nbytes < 1 << 20:
+        return 0
+    if nbytes < 1 << 24:
+        return 1
+    if nbytes < 1 << 28:
+        return 2
+    return 3
+
+
+# ---- timing ----------------------------------------------------------------
+def time_ms(fn, reps: int = 10, warmup: int = 2) -> float:
+    """Median duration of fn() over `reps` runs, each bracketed by HIP events
+    recorded on the current stream (the stream the library launches on)."""
+    for _ in range(warmup):
+        fn()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times)
+
+
+class Workload:
+    """Device operands of one tuned operation and its algorithmic bytes."""
+
+    def __init__(self, op: str, dtype: torch.dtype, n: int = 0, m: int = 0, layout: str = "row"):
+        import workloads as W
+        self.op, self.dtype, self.n, self.m, self.layout = op, dtype, n, m, layout
+        name = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}[dtype]
+        s = torch.tensor([], dtype=dtype).element_size()
+        if op in ("copy", "axpby", "dot", "nrm2"):
+            self.y = W.device_draw(n, name, 0, 1)
+            self.z = W.device_draw(n, name, 0, 2)
+            self.x = torch.empty_like(self.y)
+            self.bytes = {"copy": 2, "axpby": 3, "dot": 2, "nrm2": 1}[op] * n * s
+            self.table_op = {"copy": L.OP_COPY, "axpby": L.OP_AXPBY, "dot": L.OP_DOT, "nrm2": L.OP_DOT}[op]
+        else:  # gemv_rows / gemv_cols: y = A x with A m x n in the layout that selects the kernel
+            A = W.device_draw(m * n, name, 0, 3).view(m, n)
+            self.A = A if layout == "row" else A.t().contiguous().t()
+            self.x = W.device_draw(n, name, 0, 4)
+            self.yv = torch.empty(m, dtype=ops.default_out_dtype(dtype), device="cuda")
+            self.bytes = (m * n + m + n) * s
+            self.table_op = L.OP_GEMV_ROWS if layout == "row" else L.OP_GEMV_COLS
+        self.cls = size_class(self.bytes)
+
+    def run(self):
+        o = self.op
+        if o == "copy":
+            ops.copy(self.y, out=self.x)
+        elif o == "axpby":
+            ops.axpby(0.75, self.y, -1.25, self.z, out=self.x)
+        elif o == "dot":
+            ops.dot(self.y, self.z)
+        elif o == "nrm2":
+            ops.nrm2(self.y)
+        else:
+            ops.gemv(self.A, self.x, out=self.yv)
+
+
+def sweep(w: Workload, candidates, reps: int = 8, log=None):
+    """Time every candidate configuration on workload w.  Returns a list of
+    (config, ms, GB/s) sorted by speed."""
+    res = []
+    for cfg in candidates:
+        ops.set_config(w.table_op, w.dtype, w.cls, **cfg)
+        try:
+            ms = time_ms(w.run, reps=reps)
+        except L.BwlaError as e:  # e.g. a configuration the shape cannot use
+            if log:
+                log("skip %s: %s" % (cfg, e))
+            continue
+        res.append((cfg, ms, w.bytes / (ms * 1e-3) / 1e9))
+    ops.set_config(w.table_op, w.dtype, w.cls)
+    res.sort(key=lambda r: r[1])
+    return res
+
+
+def write_table(entries, path: str) -> None:
+    """entries: list of (op code, dtype, size class, config dict)."""
+    code = {torch.float64: L.F64, torch.float32: L.F32, torch.bfloat16: L.BF16}
+    with open(path, "w") as f:
+        f.write("# bwla tuning table: op dtype size_class block vec unroll grid increment rows split\n")
+        f.write("# written %s on %s\n" % (time.strftime("%Y-%m-%d %H:%M:%S"),
+                                          torch.cuda.get_device_name() if torch.cuda.is_available() else "?"))
+        for op, dt, cls, c in entries:
+            f.write("%d %d %d %d %d %d %d %d %d %d\n" % (
+                op, code[dt], cls, c.get("block", 0), c.get("vec", 0), c.get("unroll", 0), c.get("grid", 0),
+                c.get("increment", 0), c.get("rows", 0), c.get("split", 0)))
+
+
+def copy_proxy(results: dict) -> dict:
+    """results: {op: [(cfg, ms, GB/s), ...]} over the same vector candidate
+    list.  For each op, the rate of the copy's best configuration and of the
+    op's own best (the paper's Table 2 comparison)."""
+    best_copy = results["copy"][0][0]
+    key = json.dumps(best_copy, sort_keys=True)
+    rep = {"copy_best": best_copy}
+    for op, res in results.items():
+        own = res[0]
+        with_copy = next((r for r in res if json.dumps(r[0], sort_keys=True) == key), None)
+        rep[op] = {"own_best": own[0], "own_best_gbs": round(own[2], 1),
+                   "with_copy_cfg_gbs": round(with_copy[2], 1) if with_copy else None,
+                   "penalty_pct": round(100 * (1 - with_copy[2] / own[2]), 2) if with_copy else None}
+    return rep

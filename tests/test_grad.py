@@ -1,0 +1,118 @@
+"""Hand-written backward kernels behind torch.autograd: GEMV (dx = A^T ybar,
+dA = ybar x^T) and dot (scaled copies), checked against float64 central finite
+differences, torch.autograd.gradcheck and the oracle's gradients."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector
+from tests.gpu_util import host, mat, need_gpu, vec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (64, 48)])
+@pytest.mark.parametrize("layout", ["row", "col"])
+def test_gemv_grad_central_differences_f64(shape, layout):
+    need_gpu()
+    from paper_1409_0669_amd.autograd import GemvFn
+    m, n = shape
+    A, A64 = mat(m, n, "f64", 61, layout=layout)
+    x, x64 = vec(n, "f64", 62)
+    w, w64 = vec(m, "f64", 63)
+    A.requires_grad_(True)
+    x.requires_grad_(True)
+    y = GemvFn.apply(A, x)
+    (w * y).sum().backward()
+    gA, gx = host(A.grad), host(x.grad)
+    # L(A, x) = <w, A x> is bilinear: central differences carry no truncation
+    # error, only rounding of order u*|L|/h.
+    h = 1e-6
+    L = lambda AA, xx: oracle.dot(w64, oracle.gemv(AA, xx))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = h
+        fd = (L(A64, x64 + e) - L(A64, x64 - e)) / (2 * h)
+        assert abs(gx[j] - fd) <= 1e-7 * (1 + abs(fd))
+    for (i, j) in [(0, 0), (m - 1, n - 1), (m // 2, n // 3), (1, n - 2)]:
+        E = np.zeros((m, n))
+        E[i, j] = h
+        fd = (L(A64 + E, x64) - L(A64 - E, x64)) / (2 * h)
+        assert abs(gA[i, j] - fd) <= 1e-7 * (1 + abs(fd))
+    assert A.grad.stride() == A.stride()
+
+
+def test_gradcheck_f64():
+    need_gpu()
+    from paper_1409_0669_amd.autograd import DotFn, GemvFn
+    A = torch.randn(9, 7, dtype=torch.float64, device="cuda", requires_grad=True)
+    x = torch.randn(7, dtype=torch.float64, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda a, b: GemvFn.apply(a, b), (A, x))
+    p = torch.randn(33, dtype=torch.float64, device="cuda", requires_grad=True)
+    q = torch.randn(33, dtype=torch.float64, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda a, b: DotFn.apply(a, b), (p, q))
+
+
+@pytest.mark.parametrize("shape", [(4096, 4096), (16384, 2048), (2048, 16384)])
+def test_gemv_grad_f32_against_oracle(shape):
+    """f32 forward/backward at the differentiation shapes: dx within the
+    float32 GEMV criterion of the oracle's A^T ybar; dA bitwise equal to the
+    oracle's rounded products (sampled rows)."""
+    need_gpu()
+    from paper_1409_0669_amd.autograd import GemvFn
+    m, n = shape
+    A = W.device_draw(m * n, "f32", 0, 71).view(m, n).requires_grad_(True)
+    x = W.device_draw(n, "f32", 0, 72).requires_grad_(True)
+    yb = W.device_draw(m, "f32", 0, 73)
+    y = GemvFn.apply(A, x)
+    y.backward(yb)
+    A64, x64, yb64 = host(A.detach()), host(x.detach()), host(yb)
+    check_vector(host(y.detach()), oracle.gemv(A64, x64), np.abs(A64) @ np.abs(x64), TOL["f32"], "fwd")
+    check_vector(host(x.grad), oracle.gemv(A64, yb64, trans=1), np.abs(A64).T @ np.abs(yb64), TOL["f32"], "dx")
+    rows = np.random.default_rng(0).choice(m, 16, replace=False)
+    gA = A.grad[torch.from_numpy(rows).cuda()]
+    ref = oracle.ger("f32", yb64[rows], x64).reshape(len(rows), n)
+    assert bitwise_equal(host(gA), ref)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_dot_backward_bitwise(dtype):
+    need_gpu()
+    from paper_1409_0669_amd.autograd import DotFn
+    n = 1 << 24 if dtype == "f32" else 100_003
+    x = W.device_draw(n, dtype, 0, 81).requires_grad_(True)
+    y = W.device_draw(n, dtype, 0, 82).requires_grad_(True)
+    z = DotFn.apply(x, y)
+    zbar = torch.tensor(0.37, dtype=z.dtype, device="cuda")
+    z.backward(zbar)
+    x64, y64 = host(x.detach()), host(y.detach())
+    check_scalar(float(z.item()), oracle.dot(x64, y64), float(np.abs(x64 * y64).sum()), TOL[dtype])
+    zb = oracle.scalar(dtype, 1.0, float(zbar.item()))
+    dx_ref, dy_ref = oracle.dot_backward(dtype, zb, x64, y64)
+    assert bitwise_equal(host(x.grad), dx_ref)
+    assert bitwise_equal(host(y.grad), dy_ref)
+
+
+def test_adjoint_identity_f64():
+    need_gpu()
+    from paper_1409_0669_amd import ops
+    A, A64 = mat(700, 500, "f64", 91)
+    x, x64 = vec(500, "f64", 92)
+    w, w64 = vec(700, "f64", 93)
+    lhs = float(ops.dot(w, ops.gemv(A, x)).item())
+    rhs = float(ops.dot(ops.gemv(A, w, trans=True), x).item())
+    scale = float(np.abs(w64) @ np.abs(A64) @ np.abs(x64))
+    assert abs(lhs - rhs) <= 1e-13 * scale
+
+
+def test_needs_input_grad_respected():
+    need_gpu()
+    from paper_1409_0669_amd.autograd import GemvFn
+    A = torch.randn(30, 20, dtype=torch.float32, device="cuda")
+    x = torch.randn(20, dtype=torch.float32, device="cuda", requires_grad=True)
+    GemvFn.apply(A, x).sum().backward()
+    assert A.grad is None and x.grad is not None

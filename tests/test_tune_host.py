@@ -1,0 +1,63 @@
+"""Host logic of the autotuner: the paper's configuration space and the
+gfx950 candidate space (no GPU)."""
+from __future__ import annotations
+
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden():
+    d = {}
+    for line in open(os.path.join(HERE, "golden", "paper_config_space.txt")):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        d[k.strip()] = v.split()
+    return d
+
+
+def test_paper_space_matches_the_paper():
+    from paper_1409_0669_amd import tune
+    g = _golden()
+    sp = tune.paper_space()
+    assert len(sp) == int(g["total"][0]) == 1900
+    assert len(tune.PAPER_INCREMENTS) == int(g["increments"][0])
+    assert len(tune.PAPER_VECTOR_TYPES) == int(g["vector_types"][0])
+    assert len(tune.PAPER_LOCAL_SIZES) == int(g["local_sizes"][0])
+    assert len(tune.PAPER_GROUPS) == int(g["work_group_counts"][0])
+    assert tune.PAPER_LOCAL_SIZES[-1] == 512
+    assert set(map(int, g["extra_work_group_counts"])) <= set(tune.PAPER_GROUPS)
+    assert max(tune.PAPER_GROUPS) == 1024
+    assert len({tuple(sorted(c.items())) for c in sp}) == 1900
+
+
+def test_gfx950_space_is_valid_for_the_library():
+    import ctypes
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import tune
+    for cfg in tune.vector_space(256)[:200] + tune.rows_space()[:100] + tune.cols_space()[:100]:
+        c = L.Config(**cfg)
+        assert L.lib.bwla_set_config(L.OP_DOT, 0, 3, ctypes.byref(c)) == L.OK, cfg
+    L.lib.bwla_set_config(L.OP_DOT, 0, -1, None)
+    assert len(tune.vector_space(256)) == 5 * 5 * 3 * 2 * 7
+
+
+def test_size_class_agrees_with_library():
+    from paper_1409_0669_amd import tune
+    assert [tune.size_class(b) for b in (0, (1 << 20) - 1, 1 << 20, (1 << 24) + 5, 1 << 28, 1 << 33)] == \
+        [0, 0, 1, 2, 3, 3]
+
+
+def test_write_table_roundtrip(tmp_path):
+    import ctypes
+    import torch
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import tune
+    p = str(tmp_path / "t.txt")
+    tune.write_table([(L.OP_AXPBY, torch.float32, 3, dict(block=512, vec=8, unroll=2, grid=2048, increment=1))], p)
+    assert L.lib.bwla_load_tuning(p.encode()) == L.OK
+    c = L.Config()
+    L.lib.bwla_get_config(L.OP_AXPBY, L.F32, 0, 1 << 26, ctypes.byref(c))
+    assert (c.block, c.vec, c.unroll, c.grid, c.increment) == (512, 8, 2, 2048, 1)
+    L.lib.bwla_set_config(L.OP_AXPBY, L.F32, -1, None)
