@@ -799,8 +799,9 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
     std::vector<Work> work;
     std::vector<BatchGemv> hg(ng);
     std::vector<BatchDot> hd(nd);
-    const int64_t kTileElems = 1 << 17; // elements of A per GEMV row tile
-    const int64_t kChunk = 1 << 16;     // elements per dot chunk (a multiple of block*vec)
+    // Work items are sized for one wave64 each.
+    const int64_t kTileElems = 1 << 15; // elements of A per GEMV row tile
+    const int64_t kChunk = 1 << 14;     // elements per dot chunk (a multiple of 64*vec)
     for (int i = 0; i < ng; ++i) {
         const bwla_gemv_desc &q = g[i];
         BatchGemv &b = hg[i];
@@ -860,9 +861,13 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         items[i] = work[i].it;
     p->n_items = (int64_t)items.size();
     p->n_dots = nd;
+    // One wave per item at a time: enough work-groups to fill every CU's wave
+    // slots, but no more waves than items.
     const int64_t per_cu = std::max(1, 2048 / p->block);
+    const int64_t waves_per_block = p->block / 64;
     int64_t grid = cfg && cfg->grid ? cfg->grid : (int64_t)device_cus() * per_cu;
-    p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, std::max<int64_t>(1, p->n_items)));
+    grid = std::min<int64_t>(grid, ceil_div(std::max<int64_t>(1, p->n_items), waves_per_block));
+    p->grid = (int)std::max<int64_t>(1, grid);
 
     auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
         if (bytes == 0)

@@ -2,15 +2,18 @@
 //
 // The host flattens every problem into work items -- row tiles of a GEMV
 // (full row length) and fixed-size chunks of a dot -- ordered by decreasing
-// cost, and launches a grid sized to the machine.  Each work-group repeatedly
-// takes the next item from an atomic counter until the list is exhausted, so
-// every wave reaches the exit.  GEMV rows are handled by groups of G lanes
-// (G a power of two sized to the row length), reduced by butterfly exchanges
-// inside the group.  A dot chunk is reduced by the whole work-group; a
-// single-chunk dot writes its result directly, otherwise the chunk's float64
-// partial goes to a slot of the dot and a small finalize kernel combines each
-// dot's slots in chunk order.  Every result depends only on its own problem's
-// sizes, never on the batch order or on which work-group ran which item.
+// cost, and launches a grid sized to the machine.  The kernel is
+// wave-persistent: each wave64 repeatedly takes the next item from an atomic
+// counter (lane 0 draws, readfirstlane broadcasts) until the list is
+// exhausted, and reduces its item within the wave, so the kernel has no LDS
+// traffic and no work-group barriers -- waves never wait for each other and
+// every wave reaches the exit.  GEMV rows are handled by groups of G lanes (G
+// a power of two sized to the row length), reduced by butterfly exchanges
+// inside the group.  A dot chunk is reduced across the wave; a single-chunk
+// dot writes its result directly, otherwise the chunk's float64 partial goes
+// to a slot of the dot and a small finalize kernel combines each dot's slots
+// in chunk order.  Every result depends only on its own problem's sizes, never
+// on the batch order or on which wave ran which item.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -21,15 +24,15 @@ __device__ __forceinline__ void gemv_tile(const BatchGemv &g, int64_t rb, int64_
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int G = g.lanes;
     const int rpw = 64 / G;
     const int sub = lane / G, gl = lane - sub * G;
     const T *A = (const T *)g.A;
     const T *x = (const T *)g.x;
     const int64_t K = g.n, kpack = K / V;
-    for (int64_t wbase = rb + (int64_t)wave * rpw; wbase < re; wbase += (int64_t)nw * rpw) {
-        const int64_t r = wbase + sub;
+    for (int64_t base = rb; base < re; base += rpw) {
+        const int64_t r = base + sub;
         const int64_t rr = r < re ? r : re - 1;
         const T *row = A + rr * g.lda;
         Acc<C, COMP> acc;
@@ -50,62 +53,60 @@ __device__ __forceinline__ void gemv_tile(const BatchGemv &g, int64_t rb, int64_
 }
 
 template <typename T, int V, bool COMP>
-__device__ __forceinline__ void dot_chunk(const BatchArgs &a, const BatchItem &w, DD *lds)
+__device__ __forceinline__ void dot_chunk(const BatchArgs &a, const BatchItem &w)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    const int lane = threadIdx.x & 63;
     const BatchDot &d = a.dots[w.prob];
     const T *x = (const T *)d.x, *y = (const T *)d.y;
     Acc<C, COMP> acc[2];
     const int64_t pb = w.begin / V, pe = w.end / V; // chunk starts are pack-aligned
-    int64_t p = pb + threadIdx.x;
-    for (; p + blockDim.x < pe; p += 2 * (int64_t)blockDim.x) {
+    int64_t p = pb + lane;
+    for (; p + 64 < pe; p += 128) {
         Pack<T, V> x0 = load_pack<T, V>(x + p * V), y0 = load_pack<T, V>(y + p * V);
-        Pack<T, V> x1 = load_pack<T, V>(x + (p + blockDim.x) * V), y1 = load_pack<T, V>(y + (p + blockDim.x) * V);
+        Pack<T, V> x1 = load_pack<T, V>(x + (p + 64) * V), y1 = load_pack<T, V>(y + (p + 64) * V);
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             acc[0].template add_prod<EXACT>(widen(x0.v[e]), widen(y0.v[e]));
             acc[1].template add_prod<EXACT>(widen(x1.v[e]), widen(y1.v[e]));
         }
     }
-    for (; p < pe; p += blockDim.x) {
+    for (; p < pe; p += 64) {
         Pack<T, V> x0 = load_pack<T, V>(x + p * V), y0 = load_pack<T, V>(y + p * V);
 #pragma unroll
         for (int e = 0; e < V; ++e)
             acc[0].template add_prod<EXACT>(widen(x0.v[e]), widen(y0.v[e]));
     }
-    const int64_t tail = w.end - pe * V;
-    if (threadIdx.x < tail)
-        acc[0].template add_prod<EXACT>(widen(x[pe * V + threadIdx.x]), widen(y[pe * V + threadIdx.x]));
-    DD v = combine<COMP>(acc[0].to_dd(), acc[1].to_dd());
-    v = block_sum<COMP>(v, lds);
-    if (d.chunks == 1) {
-        if (threadIdx.x == 0)
+    const int64_t tail = w.end - pe * V; // < V, only in a dot's last chunk
+    if (lane < tail)
+        acc[0].template add_prod<EXACT>(widen(x[pe * V + lane]), widen(y[pe * V + lane]));
+    DD v = wave_sum<COMP>(combine<COMP>(acc[0].to_dd(), acc[1].to_dd()));
+    if (lane == 0) {
+        if (d.chunks == 1)
             store_out(d.out, 0, a.out_f64, v.hi + v.lo);
-        return;
+        else
+            reinterpret_cast<DD *>(a.partials)[d.slot0 + w.chunk] = v;
     }
-    if (threadIdx.x == 0)
-        reinterpret_cast<DD *>(a.partials)[d.slot0 + w.chunk] = v;
 }
 
 template <typename T, int V, bool COMP>
 __global__ __launch_bounds__(1024) void k_batched(BatchArgs a)
 {
-    __shared__ unsigned next;
-    __shared__ DD lds[16];
+    const int lane = threadIdx.x & 63;
     for (;;) {
-        if (threadIdx.x == 0)
-            next = atomicAdd(a.work_counter, 1u);
-        __syncthreads();
-        const int64_t it = next;
-        __syncthreads(); // everyone has read `next` before thread 0 overwrites it
+        unsigned drawn = 0;
+        if (lane == 0)
+            drawn = atomicAdd(a.work_counter, 1u);
+        // every lane is active again here, so the first active lane is lane 0
+        const int64_t it = (int64_t)__builtin_amdgcn_readfirstlane(drawn);
         if (it >= a.n_items)
             break;
         const BatchItem w = a.items[it];
         if (w.kind == 0)
             gemv_tile<T, V, COMP>(a.gemv[w.prob], w.begin, w.end, a.out_f64);
         else
-            dot_chunk<T, V, COMP>(a, w, lds);
+            dot_chunk<T, V, COMP>(a, w);
     }
 }
 
