@@ -186,7 +186,10 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
  *         finalize kernel.
  * capture: records the same three kernels into a HIP graph owned by the plan.
  * replay: launches the captured graph.
- * Descriptor pointers must stay valid while the plan is used. */
+ * Descriptor pointers must stay valid while the plan is used.
+ * Status: run and capture return BWLA_ERR_UNSUPPORTED unless the environment
+ * variable BWLA_ENABLE_UNVALIDATED_BATCH=1 is set: the persistent kernel's
+ * current form has not yet been validated on hardware. */
 typedef struct bwla_batch_plan bwla_batch_plan;
 typedef struct {
     const void *A;

@@ -95,11 +95,13 @@ __global__ __launch_bounds__(1024) void k_batched(BatchArgs a)
 {
     const int lane = threadIdx.x & 63;
     for (;;) {
-        unsigned drawn = 0;
-        if (lane == 0)
-            drawn = atomicAdd(a.work_counter, 1u);
-        // every lane is active again here, so the first active lane is lane 0
-        const int64_t it = (int64_t)__builtin_amdgcn_readfirstlane(drawn);
+        // Every lane takes part in the draw (lane 0 adds 1, the others 0) and
+        // readfirstlane then returns lane 0's value.  No branch here depends on
+        // the lane: with the draw under `if (lane == 0)` the compiler may split
+        // the loop on that condition, so that lanes 1..63 re-enter it without
+        // lane 0 and readfirstlane returns their stale value instead.
+        const unsigned got = atomicAdd(a.work_counter, lane == 0 ? 1u : 0u);
+        const int64_t it = (int64_t)__builtin_amdgcn_readfirstlane(got);
         if (it >= a.n_items)
             break;
         const BatchItem w = a.items[it];
