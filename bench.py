@@ -44,7 +44,31 @@ def parse():
                     help="time budget of the CPU oracle sample")
     ap.add_argument("--tuning", default=None, help="tuning table to load before timing")
     ap.add_argument("--breakdown", action="store_true", help="print per-operation rates to stderr")
+    ap.add_argument("--kernel-profile", action="store_true",
+                    help="run only the dominant kernel (GEMV 16384x16384 f64 row-major) and a calibration "
+                         "copy of 2^26 f64 (512 MiB read, 512 MiB written), --steps times each, for "
+                         "rocprofv3 kernel traces and counters")
     return ap.parse_args()
+
+
+def kernel_profile(args, torch, W, ops):
+    m = n = 16384
+    A = W.device_draw(m * n, "f64", 0, 301).reshape(m, n)
+    x = W.device_draw(n, "f64", 0, 401)
+    y = torch.empty(m, dtype=torch.float64, device="cuda")
+    src = W.device_draw(1 << 26, "f64", 0, 501)
+    dst = torch.empty_like(src)
+    for name, fn in (("gemv_rows_f64_16384", lambda: ops.gemv(A, x, out=y)),
+                     ("copy_f64_2^26", lambda: ops.copy(src, out=dst))):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        log("%-22s %d launches, %.1f us per launch (host clock)" % (name, args.steps,
+                                                                   (time.perf_counter() - t0) * 1e6 / args.steps))
 
 
 def log(*a):
@@ -157,6 +181,9 @@ def main():
         sys.exit(2)
     if args.tuning:
         ops.load_tuning(args.tuning)
+    if args.kernel_profile:
+        kernel_profile(args, torch, W, ops)
+        return
     t0 = time.perf_counter()
     work, keep = build_workload(torch, W, ops)
     torch.cuda.synchronize()

@@ -129,28 +129,32 @@ bwla_status check_cfg(const bwla_config &c)
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // --- resolved configurations ---------------------------------------------
-// Streaming and reduction kernels over n elements.
+// Defaults below come from sweeps of the configuration space on MI355X
+// (256 CUs): streaming kernels run best with one pack per thread and a grid
+// covering the vector once; reductions with one 256-thread work-group per CU
+// holding four packs in flight per thread (fewer, longer-lived waves stream
+// better and keep the second stage small).
+constexpr int kOpCg = BWLA_OP_COUNT; // internal: the fused CG update (table row of DOT)
+
 Cfg resolve_vector(int op, int t, int64_t n, std::initializer_list<const void *> ptrs, int nstreams)
 {
-    bwla_config u = lookup(op, t, (double)n * dsize(t) * nstreams);
+    const bool cg = op == kOpCg;
+    const bool reduction = op == BWLA_OP_DOT || cg;
+    bwla_config u = lookup(cg ? BWLA_OP_DOT : op, t, (double)n * dsize(t) * nstreams);
     Cfg c;
     c.block = u.block ? u.block : 256;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), ptrs);
-    c.unroll = u.unroll ? u.unroll : 4;
+    c.unroll = u.unroll ? u.unroll : (op == BWLA_OP_DOT ? 4 : 1);
     c.inc = u.increment;
     c.rows = 1;
     c.split = 1;
     const int64_t npack = std::max<int64_t>(1, n / c.vec);
     const int64_t one_pass = std::max<int64_t>(1, ceil_div(npack, (int64_t)c.block * c.unroll));
     int64_t grid = u.grid;
-    if (!grid) {
-        if (op == BWLA_OP_DOT)
-            grid = std::min<int64_t>(one_pass, (int64_t)device_cus() * 8);
-        else
-            grid = one_pass;
-    }
+    if (!grid)
+        grid = op == BWLA_OP_DOT ? std::min<int64_t>(one_pass, device_cus()) : one_pass;
     grid = std::min<int64_t>(grid, 1 << 30);
-    if (op == BWLA_OP_DOT) // partial slots and the final combine stay small
+    if (reduction) // partial slots and the second stage stay small
         grid = std::min<int64_t>(grid, 65536);
     c.grid = (int)std::max<int64_t>(grid, 1);
     return c;
@@ -160,18 +164,20 @@ Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
 {
     bwla_config u = lookup(BWLA_OP_GEMV_ROWS, t, (double)L * K * dsize(t));
     Cfg c;
-    c.block = u.block ? u.block : 256;
+    c.block = u.block ? u.block : 1024;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A, v}, ld);
     c.unroll = 1;
     c.grid = 0;
     c.inc = 0;
-    c.rows = u.rows ? u.rows : 4;
+    c.rows = u.rows ? u.rows : 2;
     const int64_t groups = std::max<int64_t>(1, ceil_div(L, c.rows));
     int64_t split = u.split;
     if (!split) {
-        const int64_t target = (int64_t)device_cus() * 8;
+        // enough work-groups for every CU to hold two, each slice at least
+        // two block-widths of packs long
+        const int64_t target = (int64_t)device_cus() * 2;
         const int64_t kpack = std::max<int64_t>(1, K / c.vec);
-        split = groups >= target / 2 ? 1 : ceil_div(target, groups);
+        split = groups >= target ? 1 : ceil_div(target, groups);
         split = std::min<int64_t>(split, std::max<int64_t>(1, kpack / (2 * c.block)));
     }
     split = std::max<int64_t>(1, std::min<int64_t>(split, std::max<int64_t>(1, K)));
@@ -184,7 +190,7 @@ Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
 {
     bwla_config u = lookup(BWLA_OP_GEMV_COLS, t, (double)L * K * dsize(t));
     Cfg c;
-    c.block = u.block ? u.block : 256;
+    c.block = u.block ? u.block : 512;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A}, ld);
     c.unroll = u.unroll ? u.unroll : 4;
     c.grid = 0;
@@ -193,7 +199,8 @@ Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
     const int64_t tiles = std::max<int64_t>(1, ceil_div(K, 64 * (int64_t)c.vec));
     int64_t split = u.split;
     if (!split) {
-        const int64_t target = (int64_t)device_cus() * 8;
+        // about one work-group per CU, each wave with at least 16 lines
+        const int64_t target = (int64_t)device_cus();
         const int64_t waves = c.block / 64;
         split = tiles >= target ? 1 : ceil_div(target, tiles);
         split = std::min<int64_t>(split, std::max<int64_t>(1, L / (waves * 16)));
@@ -511,7 +518,7 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha, 
                            void *x, const void *p, void *r, const void *q, bwla_dtype out_t, void *out,
                            void *ws, size_t ws_bytes, void *stream)
 {
-    Cfg c = resolve_vector(BWLA_OP_DOT, t, n, {x, p, r, q}, 2);
+    Cfg c = resolve_vector(kOpCg, t, n, {x, p, r, q}, 6);
     const size_t need = n > 0 ? ws_dot(c) : 0;
     bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
     if (st)
@@ -554,8 +561,10 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
     for (int v = 1; v <= 16; v <<= 1) {
         const void *fake = (const void *)(uintptr_t)(v * dsize(t));
         switch (op) {
-        case BWLA_OP_DOT:
+        case BWLA_OP_DOT: // dot, nrm2 and the fused CG update
             best = std::max(best, ws_dot(resolve_vector(BWLA_OP_DOT, t, n, {fake}, 2)));
+            best = std::max(best, ws_dot(resolve_vector(BWLA_OP_DOT, t, n, {fake}, 1)));
+            best = std::max(best, ws_dot(resolve_vector(kOpCg, t, n, {fake}, 6)));
             break;
         case BWLA_OP_GEMV_ROWS:
         case BWLA_OP_GEMV_COLS: {

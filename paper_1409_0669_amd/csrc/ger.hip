@@ -17,8 +17,9 @@ __global__ __launch_bounds__(1024) void k_ger(int64_t L, int64_t K, const T *a, 
                                               int64_t ld, int64_t kblocks)
 {
     using C = compute_t<T>;
-    const int64_t lg = blockIdx.x / kblocks;
-    const int64_t kb = blockIdx.x - lg * kblocks;
+    const int64_t lblk = xcd_block();
+    const int64_t lg = lblk / kblocks;
+    const int64_t kb = lblk - lg * kblocks;
     const int64_t k0 = (kb * blockDim.x + threadIdx.x) * V;
     if (k0 >= K)
         return;
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(1024) void k_ger(int64_t L, int64_t K, const T *a, 
 #pragma unroll
             for (int e = 0; e < V; ++e)
                 o.v[e] = narrow<T>(al * bv[e]);
-            store_pack<T, V>(dst, o);
+            store_pack_nt<T, V>(dst, o);
         } else {
 #pragma unroll
             for (int e = 0; e < V; ++e)

@@ -1,8 +1,8 @@
 // reduce.hip -- inner product <x, y> and Euclidean norm sqrt(<x, x>) (paper
 // Section 2: inner product with a work-group reduction in local memory).
 //
-// Stage 1: every thread accumulates its packs (same pack walk and increment
-// schemes as the streaming kernels) into U independent accumulators in the
+// Stage 1: every thread accumulates its packs (same pack walk, increment
+// schemes and nontemporal 16-byte loads as the streaming kernels) into U independent accumulators in the
 // compute precision, plain or compensated.  The accumulators leave the thread
 // as float64 (pairs when compensated), are summed across the wave with DPP and
 // cross-row exchanges, across the work-group through LDS, and the work-group
@@ -23,14 +23,15 @@ __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y,
     Acc<C, COMP> acc[U];
     const int64_t npack = n / V;
     int64_t begin, stride, end;
+    const int64_t lb = xcd_block();
     if (inc == 0) {
-        begin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        begin = lb * blockDim.x + threadIdx.x;
         stride = (int64_t)gridDim.x * blockDim.x;
         end = npack;
     } else {
         int64_t per = (npack + gridDim.x - 1) / gridDim.x;
         per = (per + blockDim.x - 1) / blockDim.x * blockDim.x;
-        int64_t b = (int64_t)blockIdx.x * per;
+        int64_t b = lb * per;
         begin = b + threadIdx.x;
         stride = blockDim.x;
         end = b + per < npack ? b + per : npack;
@@ -40,9 +41,9 @@ __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y,
         Pack<T, V> vx[U], vy[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            vx[u] = load_pack<T, V>(x + (p + u * stride) * V);
+            vx[u] = load_pack_nt<T, V>(x + (p + u * stride) * V);
             if constexpr (!SQ)
-                vy[u] = load_pack<T, V>(y + (p + u * stride) * V);
+                vy[u] = load_pack_nt<T, V>(y + (p + u * stride) * V);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -54,9 +55,9 @@ __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y,
             }
     }
     for (; p < end; p += stride) {
-        Pack<T, V> vx = load_pack<T, V>(x + p * V), vy;
+        Pack<T, V> vx = load_pack_nt<T, V>(x + p * V), vy;
         if constexpr (!SQ)
-            vy = load_pack<T, V>(y + p * V);
+            vy = load_pack_nt<T, V>(y + p * V);
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             C a = widen(vx.v[e]);

@@ -5,7 +5,8 @@
 // Work decomposition.  The vector is cut into packs of V consecutive elements
 // (the paper's vector data types).  Each thread handles U packs per loop trip,
 // all loads issued before any arithmetic, so U*V*sizeof(T) bytes per thread
-// are in flight.  The loop increment is either the whole grid (GLOBAL, the
+// are in flight; every access is a 16-byte nontemporal one (the data is
+// touched once).  The loop increment is either the whole grid (GLOBAL, the
 // paper's first skeleton) or the work-group inside one contiguous chunk per
 // work-group (LOCAL, the paper's second skeleton; chunks are multiples of the
 // work-group size so accesses stay aligned).  The n % V tail elements are
@@ -20,17 +21,19 @@ struct Range {
 };
 
 // Pack indices visited by this thread under the chosen increment scheme.
+// Work-groups are numbered XCD-contiguously (xcd_block).
 __device__ __forceinline__ Range pack_range(int64_t npack, int inc)
 {
     Range r;
+    const int64_t lb = xcd_block();
     if (inc == 0) {
-        r.begin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        r.begin = lb * blockDim.x + threadIdx.x;
         r.stride = (int64_t)gridDim.x * blockDim.x;
         r.end = npack;
     } else {
         int64_t per = (npack + gridDim.x - 1) / gridDim.x;
         per = (per + blockDim.x - 1) / blockDim.x * blockDim.x;
-        int64_t b = (int64_t)blockIdx.x * per;
+        int64_t b = lb * per;
         r.begin = b + threadIdx.x;
         r.stride = blockDim.x;
         r.end = b + per < npack ? b + per : npack;
@@ -51,13 +54,13 @@ __global__ __launch_bounds__(1024) void k_copy(int64_t n, const T *y, T *x, int 
         Pack<T, V> v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            v[u] = load_pack<T, V>(y + (p + u * rg.stride) * V);
+            v[u] = load_pack_nt<T, V>(y + (p + u * rg.stride) * V);
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            store_pack<T, V>(x + (p + u * rg.stride) * V, v[u]);
+            store_pack_nt<T, V>(x + (p + u * rg.stride) * V, v[u]);
     }
     for (; p < rg.end; p += rg.stride)
-        store_pack<T, V>(x + p * V, load_pack<T, V>(y + p * V));
+        store_pack_nt<T, V>(x + p * V, load_pack_nt<T, V>(y + p * V));
     const int64_t tail = n - npack * V;
     if (blockIdx.x == 0 && threadIdx.x < tail)
         x[npack * V + threadIdx.x] = y[npack * V + threadIdx.x];
@@ -89,8 +92,8 @@ __global__ __launch_bounds__(1024) void k_axpby(int64_t n, compute_t<T> a, const
         Pack<T, V> vy[U], vz[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            vy[u] = load_pack<T, V>(y + (p + u * rg.stride) * V);
-            vz[u] = load_pack<T, V>(z + (p + u * rg.stride) * V);
+            vy[u] = load_pack_nt<T, V>(y + (p + u * rg.stride) * V);
+            vz[u] = load_pack_nt<T, V>(z + (p + u * rg.stride) * V);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -98,15 +101,15 @@ __global__ __launch_bounds__(1024) void k_axpby(int64_t n, compute_t<T> a, const
 #pragma unroll
             for (int e = 0; e < V; ++e)
                 o.v[e] = axpby_elem<T>(a, vy[u].v[e], b, vz[u].v[e]);
-            store_pack<T, V>(x + (p + u * rg.stride) * V, o);
+            store_pack_nt<T, V>(x + (p + u * rg.stride) * V, o);
         }
     }
     for (; p < rg.end; p += rg.stride) {
-        Pack<T, V> vy = load_pack<T, V>(y + p * V), vz = load_pack<T, V>(z + p * V), o;
+        Pack<T, V> vy = load_pack_nt<T, V>(y + p * V), vz = load_pack_nt<T, V>(z + p * V), o;
 #pragma unroll
         for (int e = 0; e < V; ++e)
             o.v[e] = axpby_elem<T>(a, vy.v[e], b, vz.v[e]);
-        store_pack<T, V>(x + p * V, o);
+        store_pack_nt<T, V>(x + p * V, o);
     }
     const int64_t tail = n - npack * V;
     if (blockIdx.x == 0 && threadIdx.x < tail) {
@@ -138,10 +141,10 @@ __global__ __launch_bounds__(1024) void k_cg(int64_t n, compute_t<T> a, const co
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t o = (i + u * rg.stride) * V;
-            vx[u] = load_pack<T, V>(x + o);
-            vp[u] = load_pack<T, V>(p + o);
-            vr[u] = load_pack<T, V>(r + o);
-            vq[u] = load_pack<T, V>(q + o);
+            vx[u] = load_pack_nt<T, V>(x + o);
+            vp[u] = load_pack_nt<T, V>(p + o);
+            vr[u] = load_pack_nt<T, V>(r + o);
+            vq[u] = load_pack_nt<T, V>(q + o);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -153,14 +156,14 @@ __global__ __launch_bounds__(1024) void k_cg(int64_t n, compute_t<T> a, const co
                 C rn = widen(vr[u].v[e]);
                 acc[u].template add_prod<EXACT>(rn, rn);
             }
-            store_pack<T, V>(x + o, vx[u]);
-            store_pack<T, V>(r + o, vr[u]);
+            store_pack_nt<T, V>(x + o, vx[u]);
+            store_pack_nt<T, V>(r + o, vr[u]);
         }
     }
     for (; i < rg.end; i += rg.stride) {
         const int64_t o = i * V;
-        Pack<T, V> vx = load_pack<T, V>(x + o), vp = load_pack<T, V>(p + o);
-        Pack<T, V> vr = load_pack<T, V>(r + o), vq = load_pack<T, V>(q + o);
+        Pack<T, V> vx = load_pack_nt<T, V>(x + o), vp = load_pack_nt<T, V>(p + o);
+        Pack<T, V> vr = load_pack_nt<T, V>(r + o), vq = load_pack_nt<T, V>(q + o);
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             vx.v[e] = axpby_elem<T>(a, vp.v[e], one, vx.v[e]);
@@ -168,8 +171,8 @@ __global__ __launch_bounds__(1024) void k_cg(int64_t n, compute_t<T> a, const co
             C rn = widen(vr.v[e]);
             acc[0].template add_prod<EXACT>(rn, rn);
         }
-        store_pack<T, V>(x + o, vx);
-        store_pack<T, V>(r + o, vr);
+        store_pack_nt<T, V>(x + o, vx);
+        store_pack_nt<T, V>(r + o, vr);
     }
     const int64_t tail = n - npack * V;
     if (blockIdx.x == 0 && threadIdx.x < tail) {
