@@ -44,6 +44,8 @@ def parse():
                     help="time budget of the CPU oracle sample")
     ap.add_argument("--tuning", default=None, help="tuning table to load before timing")
     ap.add_argument("--breakdown", action="store_true", help="print per-operation rates to stderr")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the adjoint, reduced-precision and composite rows")
     ap.add_argument("--kernel-profile", action="store_true",
                     help="run only the dominant kernel (GEMV 16384x16384 f64 row-major) and a calibration "
                          "copy of 2^26 f64 (512 MiB read, 512 MiB written), --steps times each, for "
@@ -107,6 +109,91 @@ def build_workload(torch, W, ops):
             work.append((("gemv", dt, "row", m), nbytes, lambda A=A_row, x=xv, y=yv_r: ops.gemv(A, x, out=y)))
             work.append((("gemv", dt, "col", m), nbytes, lambda A=A_col, x=xv, y=yv_c: ops.gemv(A, x, out=y)))
     return work, keep
+
+
+def _median_ms(torch, fn, reps):
+    times = []
+    fn()
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def extra_rows(torch, W, ops, reps):
+    """The other rows of the hot path, each timed on its own (median of `reps`
+    HIP-event intervals on the launch stream), outside the main metric:
+    adjoint kernels at the differentiation shapes, reduced-precision storage
+    with compensated accumulation, and the composite operations."""
+    from paper_1409_0669_amd import composite
+    out = {}
+
+    def rate(name, nbytes, fn):
+        ms = _median_ms(torch, fn, reps)
+        out[name] = {"GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1), "us": round(ms * 1e3, 1)}
+
+    # adjoints (float32): y = A x, dx = A^T ybar, dA = ybar x^T; dot backward
+    for (m, n) in W.ADJOINT["gemv_shapes"]:
+        A = W.device_draw(m * n, "f32", 0, 900).view(m, n)
+        x = W.device_draw(n, "f32", 0, 901)
+        yb = W.device_draw(m, "f32", 0, 902)
+        y = torch.empty(m, dtype=torch.float32, device="cuda")
+        dx = torch.empty(n, dtype=torch.float32, device="cuda")
+        dA = torch.empty_like(A)
+        nb = (m * n + m + n) * 4
+        rate("adjoint gemv fwd f32 %dx%d" % (m, n), nb, lambda: ops.gemv(A, x, out=y))
+        rate("adjoint dx=A^T ybar f32 %dx%d" % (m, n), nb, lambda: ops.gemv(A, yb, trans=True, out=dx))
+        rate("adjoint dA=ybar x^T f32 %dx%d" % (m, n), nb, lambda: ops.ger(yb, x, dA))
+        del A, dA
+    nd = W.ADJOINT["dot_n"]
+    xv = W.device_draw(nd, "f32", 0, 903)
+    yv = W.device_draw(nd, "f32", 0, 904)
+    zb = torch.tensor([0.37], dtype=torch.float32, device="cuda")
+    gx, gy = torch.empty_like(xv), torch.empty_like(yv)
+    rate("adjoint dot backward f32 n=2^24", 4 * nd * 4,
+         lambda: (ops.axpby(1.0, yv, 0.0, yv, out=gx, alpha_dev=zb), ops.axpby(1.0, xv, 0.0, xv, out=gy, alpha_dev=zb)))
+    del xv, yv, gx, gy
+    # reduced precision: bf16 and f32 storage, float32 accumulation
+    n = 1 << 26
+    for dt in ("bf16", "f32"):
+        s = 2 if dt == "bf16" else 4
+        a = W.device_draw(n, dt, 0, 910)
+        b = W.device_draw(n, dt, 0, 911)
+        c = torch.empty_like(a)
+        rate("precision axpby %s n=2^26" % dt, 3 * n * s, lambda: ops.axpby(0.75, a, -1.25, b, out=c))
+        for acc in ("plain", "compensated"):
+            rate("precision dot %s %s n=2^26" % (dt, acc), 2 * n * s, lambda acc=acc: ops.dot(a, b, acc=acc))
+            rate("precision nrm2 %s %s n=2^26" % (dt, acc), n * s, lambda acc=acc: ops.nrm2(a, acc=acc))
+        del a, b, c
+        m = 16384
+        A = W.device_draw(m * m, dt, 0, 912).view(m, m)
+        x = W.device_draw(m, dt, 0, 913)
+        y = torch.empty(m, dtype=torch.float32, device="cuda")
+        for acc in ("plain", "compensated"):
+            rate("precision gemv %s %s 16384^2" % (dt, acc), (m * m + 2 * m) * s,
+                 lambda acc=acc: ops.gemv(A, x, acc=acc, out=y))
+        del A
+    # composite (float64, normal entries)
+    n = W.COMPOSITE["n"]
+    v = {k: W.device_draw(n, "f64", 0, 920 + i, dist="normal") for i, k in enumerate("xprq")}
+    rate("composite cg step 3 calls n=2^24 (7n f64)", 7 * n * 8,
+         lambda: composite.cg_step(1e-9, v["x"], v["p"], v["r"], v["q"]))
+    rate("composite cg step fused n=2^24 (7n f64 of work)", 7 * n * 8,
+         lambda: composite.cg_step_fused(1e-9, v["x"], v["p"], v["r"], v["q"]))
+    del v
+    m = W.COMPOSITE["gemv"][0]
+    A = W.device_draw(m * m, "f64", 0, 930, dist="normal").view(m, m)
+    pv = W.device_draw(m, "f64", 0, 931, dist="normal")
+    q = torch.empty(m, dtype=torch.float64, device="cuda")
+    rate("composite gemv 8192^2 + dot f64", (m * m + 3 * m) * 8, lambda: composite.gemv_dot(A, pv, q=q))
+    del A
+    out["batched"] = "not measured: the persistent batched kernel is disabled until validated on hardware"
+    return out
 
 
 def cpu_baseline(W, oracle, seconds):
@@ -228,6 +315,14 @@ def main():
         for k, v in breakdown.items():
             log("%-28s %9.1f GB/s" % (k, v))
 
+    extra = None
+    if not args.no_extra:
+        log("timing the adjoint, reduced-precision and composite rows")
+        extra = extra_rows(torch, W, ops, reps=max(5, args.steps))
+        if args.breakdown:
+            for k, v in extra.items():
+                log("%-52s %s" % (k, v))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -242,7 +337,7 @@ def main():
         "config": {"workload": "paper-scale plain kernels: axpby, dot, nrm2 at n=1e5,1e6,1e7,2^26 and GEMV "
                                "4096^2, 16384^2 row- and column-major; f32 and f64; uniform[-1,1) seed 0",
                    "bytes_per_step": step_bytes, "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
-        "roofline": roofline, "cpu_baseline": cpu, "breakdown_gbs": breakdown,
+        "roofline": roofline, "cpu_baseline": cpu, "breakdown_gbs": breakdown, "other_rows": extra,
     }
     print(json.dumps(line), flush=True)
     del keep

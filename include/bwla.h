@@ -74,17 +74,19 @@ typedef enum { BWLA_INC_GLOBAL = 0, BWLA_INC_LOCAL = 1 } bwla_increment;
 typedef enum {
     BWLA_OP_COPY = 0,
     BWLA_OP_AXPBY = 1,
-    BWLA_OP_DOT = 2,       /* also used by nrm2 */
+    BWLA_OP_DOT = 2,
     BWLA_OP_GEMV_ROWS = 3, /* each output is a reduction along a contiguous line of A */
     BWLA_OP_GEMV_COLS = 4, /* each output runs along a contiguous line; reduction across lines */
     BWLA_OP_GER = 5,
-    BWLA_OP_COUNT = 6
+    BWLA_OP_NRM2 = 6,
+    BWLA_OP_CG = 7,        /* the fused CG-style update */
+    BWLA_OP_COUNT = 8
 } bwla_op;
 
 /* Kernel configuration: the paper's triple (kernel source, local work size,
  * global work size; Section 1 and Section 2) with the source variant spelled
  * out.  A zero field means "library default".  Which fields an op uses:
- *   COPY, AXPBY, DOT: block, vec, unroll, grid, increment
+ *   COPY, AXPBY, DOT, NRM2, CG: block, vec, unroll, grid, increment
  *   GEMV_ROWS:        block, vec, rows (lines per block), split (blocks along a line)
  *   GEMV_COLS:        block, vec, unroll (lines in flight), split (blocks across lines)
  *   GER:              block, vec, rows
@@ -165,10 +167,11 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha,
                            size_t ws_bytes, void *stream);
 
 /* Bytes of workspace that the call with these arguments needs under the
- * current configuration table.  `op` is the public operation: BWLA_OP_DOT for
- * dot/nrm2/cg_update (m ignored, n = length), BWLA_OP_GEMV_ROWS or
- * BWLA_OP_GEMV_COLS are both accepted for bwla_gemv (the kernel is chosen
- * from layout and trans). */
+ * current configuration table.  `op` is the public operation: BWLA_OP_DOT,
+ * BWLA_OP_NRM2 or BWLA_OP_CG (m ignored, n = length; any of the three gives
+ * a size that serves all three), BWLA_OP_GEMV_ROWS or BWLA_OP_GEMV_COLS for
+ * bwla_gemv (either is accepted: the kernel is chosen from layout and
+ * trans). */
 bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_layout layout,
                                 int trans, int64_t m, int64_t n, size_t *bytes);
 
@@ -219,7 +222,9 @@ void bwla_batch_plan_destroy(bwla_batch_plan *p);
  * One entry per (op, storage type, size class).  Size class by the bytes the
  * call streams: 0 < 1 MiB, 1 < 16 MiB, 2 < 256 MiB, 3 otherwise; pass -1 to
  * set every class.  cfg == NULL restores the defaults.  The table is shared
- * by all threads (mutex-guarded). */
+ * by all threads (mutex-guarded).  If the environment variable BWLA_TUNING
+ * names a tuning table, it is loaded before the first call resolves a
+ * configuration. */
 bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int size_class, const bwla_config *cfg);
 /* The configuration a call with this op, type and shape would use after
  * defaults are resolved (m = lines, n = line length for GEMV/GER; m ignored

@@ -82,8 +82,23 @@ int size_class(double bytes)
     return 3;
 }
 
+bool load_table_file(const char *path, std::string *err);
+
+// A table named by BWLA_TUNING is loaded once, before the first lookup.
+void load_env_table_once()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *p = getenv("BWLA_TUNING");
+        std::string err;
+        if (p && p[0] && !load_table_file(p, &err))
+            fprintf(stderr, "bwla: ignoring BWLA_TUNING=%s: %s\n", p, err.c_str());
+    });
+}
+
 bwla_config lookup(int op, int t, double bytes)
 {
+    load_env_table_once();
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     return g_table[op][t][size_class(bytes)];
 }
@@ -134,25 +149,30 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // covering the vector once; reductions with one 256-thread work-group per CU
 // holding four packs in flight per thread (fewer, longer-lived waves stream
 // better and keep the second stage small).
-constexpr int kOpCg = BWLA_OP_COUNT; // internal: the fused CG update (table row of DOT)
+constexpr int kOpCg = BWLA_OP_CG;
 
 Cfg resolve_vector(int op, int t, int64_t n, std::initializer_list<const void *> ptrs, int nstreams)
 {
-    const bool cg = op == kOpCg;
-    const bool reduction = op == BWLA_OP_DOT || cg;
-    bwla_config u = lookup(cg ? BWLA_OP_DOT : op, t, (double)n * dsize(t) * nstreams);
+    const bool reduction = op == BWLA_OP_DOT || op == BWLA_OP_NRM2 || op == BWLA_OP_CG;
+    bwla_config u = lookup(op, t, (double)n * dsize(t) * nstreams);
     Cfg c;
     c.block = u.block ? u.block : 256;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), ptrs);
-    c.unroll = u.unroll ? u.unroll : (op == BWLA_OP_DOT ? 4 : 1);
+    c.unroll = u.unroll ? u.unroll : (op == BWLA_OP_DOT || op == BWLA_OP_NRM2 ? 4 : 1);
     c.inc = u.increment;
     c.rows = 1;
     c.split = 1;
     const int64_t npack = std::max<int64_t>(1, n / c.vec);
     const int64_t one_pass = std::max<int64_t>(1, ceil_div(npack, (int64_t)c.block * c.unroll));
     int64_t grid = u.grid;
-    if (!grid)
-        grid = op == BWLA_OP_DOT ? std::min<int64_t>(one_pass, device_cus()) : one_pass;
+    if (!grid) {
+        if (op == BWLA_OP_DOT)
+            grid = std::min<int64_t>(one_pass, device_cus());
+        else if (op == BWLA_OP_NRM2) // one stream: twice the work-groups for the bytes in flight
+            grid = std::min<int64_t>(one_pass, 2 * (int64_t)device_cus());
+        else
+            grid = one_pass;
+    }
     grid = std::min<int64_t>(grid, 1 << 30);
     if (reduction) // partial slots and the second stage stay small
         grid = std::min<int64_t>(grid, 65536);
@@ -239,6 +259,52 @@ size_t ws_cols(const Cfg &c, int64_t K)
     if (c.split <= 1)
         return 0;
     return (size_t)ceil_div(K, 64 * (int64_t)c.vec) * c.split * 64 * c.vec * sizeof(DD);
+}
+
+// Parses a tuning table ("op dtype size_class block vec unroll grid increment
+// rows split" per line, '#' comments) and installs it atomically: either
+// every entry is valid and applied, or nothing changes.
+bool load_table_file(const char *path, std::string *err)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        *err = std::string("cannot open ") + path;
+        return false;
+    }
+    char line[512];
+    int lineno = 0;
+    struct Entry {
+        int op, t, k;
+        bwla_config c;
+    };
+    std::vector<Entry> entries;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        char *hash = strchr(line, '#');
+        if (hash)
+            *hash = 0;
+        Entry e{};
+        int got = sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &e.op, &e.t, &e.k, &e.c.block, &e.c.vec,
+                         &e.c.unroll, &e.c.grid, &e.c.increment, &e.c.rows, &e.c.split);
+        if (got <= 0)
+            continue; // blank or comment line
+        if (got != 10 || e.op < 0 || e.op >= BWLA_OP_COUNT || !valid_dtype(e.t) || e.k < -1 ||
+            e.k >= kClasses || check_cfg(e.c) != BWLA_OK) {
+            fclose(f);
+            char buf[600];
+            snprintf(buf, sizeof buf, "%s:%d: malformed tuning entry", path, lineno);
+            *err = buf;
+            return false;
+        }
+        entries.push_back(e);
+    }
+    fclose(f);
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    for (const Entry &e : entries)
+        for (int k = 0; k < kClasses; ++k)
+            if (e.k < 0 || e.k == k)
+                g_table[e.op][e.t][k] = e.c;
+    return true;
 }
 
 // --- overlap checks ----------------------------------------------------------
@@ -372,7 +438,7 @@ static bwla_status dot_common(bwla_dtype t, bwla_acc acc, int64_t n, const void 
                               bool square, bwla_dtype out_t, void *out, void *ws, size_t ws_bytes,
                               void *stream)
 {
-    Cfg c = resolve_vector(BWLA_OP_DOT, t, n, {x, y}, square ? 1 : 2);
+    Cfg c = resolve_vector(square ? BWLA_OP_NRM2 : BWLA_OP_DOT, t, n, {x, y}, square ? 1 : 2);
     const size_t need = n > 0 ? ws_dot(c) : 0;
     bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
     if (st)
@@ -561,9 +627,11 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
     for (int v = 1; v <= 16; v <<= 1) {
         const void *fake = (const void *)(uintptr_t)(v * dsize(t));
         switch (op) {
-        case BWLA_OP_DOT: // dot, nrm2 and the fused CG update
+        case BWLA_OP_DOT: // dot, nrm2 and the fused CG update share one sizing
+        case BWLA_OP_NRM2:
+        case BWLA_OP_CG:
             best = std::max(best, ws_dot(resolve_vector(BWLA_OP_DOT, t, n, {fake}, 2)));
-            best = std::max(best, ws_dot(resolve_vector(BWLA_OP_DOT, t, n, {fake}, 1)));
+            best = std::max(best, ws_dot(resolve_vector(BWLA_OP_NRM2, t, n, {fake}, 1)));
             best = std::max(best, ws_dot(resolve_vector(kOpCg, t, n, {fake}, 6)));
             break;
         case BWLA_OP_GEMV_ROWS:
@@ -625,6 +693,8 @@ bwla_status bwla_get_config(bwla_op op, bwla_dtype t, int64_t m, int64_t n, bwla
     case BWLA_OP_COPY: c = resolve_vector(op, t, n, {}, 2); break;
     case BWLA_OP_AXPBY: c = resolve_vector(op, t, n, {}, 3); break;
     case BWLA_OP_DOT: c = resolve_vector(op, t, n, {}, 2); break;
+    case BWLA_OP_NRM2: c = resolve_vector(op, t, n, {}, 1); break;
+    case BWLA_OP_CG: c = resolve_vector(op, t, n, {}, 6); break;
     case BWLA_OP_GEMV_ROWS: c = resolve_rows(t, m, n, nullptr, 0, nullptr); break;
     case BWLA_OP_GEMV_COLS: c = resolve_cols(t, m, n, nullptr, 0, nullptr); break;
     case BWLA_OP_GER: c = resolve_ger(t, m, n, nullptr, nullptr, nullptr, 0); break;
@@ -644,39 +714,10 @@ bwla_status bwla_load_tuning(const char *path)
 {
     if (!path)
         return fail(BWLA_ERR_INVALID_ARG, "path is NULL");
-    FILE *f = fopen(path, "r");
-    if (!f)
-        return fail(BWLA_ERR_INVALID_ARG, "cannot open %s", path);
-    char line[512];
-    int lineno = 0;
-    struct Entry {
-        int op, t, k;
-        bwla_config c;
-    };
-    std::vector<Entry> entries;
-    while (fgets(line, sizeof line, f)) {
-        ++lineno;
-        char *hash = strchr(line, '#');
-        if (hash)
-            *hash = 0;
-        Entry e{};
-        int got = sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &e.op, &e.t, &e.k, &e.c.block, &e.c.vec,
-                         &e.c.unroll, &e.c.grid, &e.c.increment, &e.c.rows, &e.c.split);
-        if (got <= 0)
-            continue; // blank or comment line
-        if (got != 10 || e.op < 0 || e.op >= BWLA_OP_COUNT || !valid_dtype(e.t) || e.k < -1 ||
-            e.k >= kClasses || check_cfg(e.c) != BWLA_OK) {
-            fclose(f);
-            return fail(BWLA_ERR_INVALID_ARG, "%s:%d: malformed tuning entry", path, lineno);
-        }
-        entries.push_back(e);
-    }
-    fclose(f);
-    std::lock_guard<std::mutex> lk(g_cfg_mu);
-    for (const Entry &e : entries)
-        for (int k = 0; k < kClasses; ++k)
-            if (e.k < 0 || e.k == k)
-                g_table[e.op][e.t][k] = e.c;
+    load_env_table_once(); // so a later first lookup cannot overwrite this table
+    std::string err;
+    if (!load_table_file(path, &err))
+        return fail(BWLA_ERR_INVALID_ARG, "%s", err.c_str());
     return BWLA_OK;
 }
 

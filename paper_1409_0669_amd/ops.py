@@ -271,7 +271,29 @@ def load_tuning(path: str) -> None:
     check(lib.bwla_load_tuning(path.encode()))
 
 
+def default_table_path() -> str:
+    import os
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "gfx950.txt")
+
+
+def load_default_tuning() -> bool:
+    """Load the tuning table shipped with the package (measured on MI355X),
+    unless BWLA_TUNING names another table (the library loads that one itself).
+    Returns True if the shipped table was loaded."""
+    import os
+    if os.environ.get("BWLA_TUNING"):
+        return False
+    path = default_table_path()
+    if os.path.exists(path):
+        load_tuning(path)
+        return True
+    return False
+
+
 def reset_config() -> None:
-    for op in range(6):
+    for op in range(L.OP_COUNT):
         for t in (torch.float64, torch.float32, torch.bfloat16):
             set_config(op, t)
+
+
+load_default_tuning()

@@ -107,12 +107,22 @@ class Workload:
         self.op, self.dtype, self.n, self.m, self.layout = op, dtype, n, m, layout
         name = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}[dtype]
         s = torch.tensor([], dtype=dtype).element_size()
-        if op in ("copy", "axpby", "dot", "nrm2"):
+        if op in ("copy", "axpby", "dot", "nrm2", "cg"):
             self.y = W.device_draw(n, name, 0, 1)
             self.z = W.device_draw(n, name, 0, 2)
             self.x = torch.empty_like(self.y)
-            self.bytes = {"copy": 2, "axpby": 3, "dot": 2, "nrm2": 1}[op] * n * s
-            self.table_op = {"copy": L.OP_COPY, "axpby": L.OP_AXPBY, "dot": L.OP_DOT, "nrm2": L.OP_DOT}[op]
+            if op == "cg":
+                self.r = W.device_draw(n, name, 0, 5)
+                self.x.copy_(W.device_draw(n, name, 0, 6))
+            self.bytes = {"copy": 2, "axpby": 3, "dot": 2, "nrm2": 1, "cg": 6}[op] * n * s
+            self.table_op = {"copy": L.OP_COPY, "axpby": L.OP_AXPBY, "dot": L.OP_DOT, "nrm2": L.OP_NRM2,
+                             "cg": L.OP_CG}[op]
+        elif op == "ger":  # A <- u v^T, A m x n row-major
+            self.A = torch.empty(m, n, dtype=dtype, device="cuda")
+            self.u = W.device_draw(m, name, 0, 7)
+            self.v = W.device_draw(n, name, 0, 8)
+            self.bytes = (m * n + m + n) * s
+            self.table_op = L.OP_GER
         else:  # gemv_rows / gemv_cols: y = A x with A m x n in the layout that selects the kernel
             A = W.device_draw(m * n, name, 0, 3).view(m, n)
             self.A = A if layout == "row" else A.t().contiguous().t()
@@ -132,6 +142,11 @@ class Workload:
             ops.dot(self.y, self.z)
         elif o == "nrm2":
             ops.nrm2(self.y)
+        elif o == "cg":
+            # a tiny step keeps the iterates bounded over many repetitions
+            ops.cg_update(1e-9, self.x, self.y, self.r, self.z)
+        elif o == "ger":
+            ops.ger(self.u, self.v, self.A)
         else:
             ops.gemv(self.A, self.x, out=self.yv)
 
@@ -181,3 +196,121 @@ def copy_proxy(results: dict) -> dict:
                    "with_copy_cfg_gbs": round(with_copy[2], 1) if with_copy else None,
                    "penalty_pct": round(100 * (1 - with_copy[2] / own[2]), 2) if with_copy else None}
     return rep
+
+
+# ---- the tuning run -------------------------------------------------------
+import os as _os
+
+DEFAULT_TABLE = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "tuning", "gfx950.txt")
+_DT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+
+
+def _vector_candidates(dtype, cus, quick):
+    native = 16 // torch.tensor([], dtype=dtype).element_size()
+    vecs = (native,) if quick else (max(1, native // 2), native, min(16, 2 * native))
+    blocks = (256, 1024) if quick else (128, 256, 512, 1024)
+    return [dict(block=b, vec=v, unroll=u, increment=i, grid=g * cus)
+            for b in blocks for v in vecs for u in (1, 2, 4) for i in (0, 1) for g in (1, 2, 4, 0)]
+
+
+def _rows_candidates(dtype, quick):
+    native = 16 // torch.tensor([], dtype=dtype).element_size()
+    vecs = (native,) if quick else (max(1, native // 2), native)
+    return [dict(block=b, vec=v, rows=r, split=s) for b in (256, 512, 1024) for v in vecs
+            for r in (1, 2, 4, 8) for s in (0, 1, 2, 4)]
+
+
+def _cols_candidates(dtype, quick):
+    native = 16 // torch.tensor([], dtype=dtype).element_size()
+    vecs = (native,) if quick else (max(1, native // 2), native)
+    return [dict(block=b, vec=v, unroll=u, split=s) for b in (256, 512, 1024) for v in vecs
+            for u in (2, 4) for s in (0, 1, 2, 4, 8, 16)]
+
+
+def _ger_candidates(dtype, quick):
+    native = 16 // torch.tensor([], dtype=dtype).element_size()
+    return [dict(block=b, vec=v, rows=r) for b in (128, 256, 512, 1024)
+            for v in (max(1, native // 2), native, min(16, 2 * native)) for r in (1, 2, 4, 8)]
+
+
+def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
+    """Sweep every operation, storage type and size class; return the table
+    entries and a report (best and default rates, copy proxy)."""
+    cus = L.lib.bwla_device_cus()
+    ops.reset_config()
+    entries, report = [], {"device": torch.cuda.get_device_name(), "cus": cus, "results": [], "copy_proxy": {}}
+    vec_sizes = (1 << 16, 1 << 20, 1 << 23, 1 << 26)
+    for dn in dtypes:
+        dt = _DT[dn]
+        cands = _vector_candidates(dt, cus, quick)
+        proxy_in = {}
+        for op in ("copy", "axpby", "dot", "nrm2", "cg"):
+            best_for_class = {}
+            for n in vec_sizes:
+                w = Workload(op, dt, n=n)
+                default_ms = time_ms(w.run, reps=10)
+                res = sweep(w, cands, reps=6)
+                best = res[0]
+                best_for_class[w.cls] = best[0]  # larger sizes overwrite smaller ones in the same class
+                report["results"].append({"op": op, "dtype": dn, "n": n, "class": w.cls, "bytes": w.bytes,
+                                          "best": best[0], "best_gbs": round(best[2], 1),
+                                          "default_gbs": round(w.bytes / (default_ms * 1e-3) / 1e9, 1)})
+                log("%-5s %-4s n=%-9d class %d best %7.1f GB/s default %7.1f GB/s %s" % (
+                    op, dn, n, w.cls, best[2], w.bytes / (default_ms * 1e-3) / 1e9, best[0]))
+                if n == vec_sizes[-1] and op != "cg":
+                    proxy_in[op] = res
+                del w
+            for cls, cfg in best_for_class.items():
+                entries.append((Workload_table_op(op), dt, cls, cfg))
+        report["copy_proxy"][dn] = copy_proxy(proxy_in)
+        for (m, n) in ((1024, 1024), (4096, 4096), (16384, 16384)):
+            for layout, cands_g in (("row", _rows_candidates(dt, quick)), ("col", _cols_candidates(dt, quick))):
+                w = Workload("gemv", dt, n=n, m=m, layout=layout)
+                default_ms = time_ms(w.run, reps=10)
+                res = sweep(w, cands_g, reps=6)
+                entries.append((w.table_op, dt, w.cls, res[0][0]))
+                report["results"].append({"op": "gemv_" + layout, "dtype": dn, "m": m, "n": n, "class": w.cls,
+                                          "bytes": w.bytes, "best": res[0][0], "best_gbs": round(res[0][2], 1),
+                                          "default_gbs": round(w.bytes / (default_ms * 1e-3) / 1e9, 1)})
+                log("gemv %s %-4s %dx%d class %d best %7.1f GB/s default %7.1f GB/s %s" % (
+                    layout, dn, m, n, w.cls, res[0][2], w.bytes / (default_ms * 1e-3) / 1e9, res[0][0]))
+                del w
+        for (m, n) in ((4096, 4096), (16384, 16384)):
+            w = Workload("ger", dt, n=n, m=m)
+            default_ms = time_ms(w.run, reps=10)
+            res = sweep(w, _ger_candidates(dt, quick), reps=6)
+            entries.append((L.OP_GER, dt, w.cls, res[0][0]))
+            report["results"].append({"op": "ger", "dtype": dn, "m": m, "n": n, "class": w.cls, "bytes": w.bytes,
+                                      "best": res[0][0], "best_gbs": round(res[0][2], 1),
+                                      "default_gbs": round(w.bytes / (default_ms * 1e-3) / 1e9, 1)})
+            log("ger %-4s %dx%d class %d best %7.1f GB/s default %7.1f GB/s %s" % (
+                dn, m, n, w.cls, res[0][2], w.bytes / (default_ms * 1e-3) / 1e9, res[0][0]))
+            del w
+    return entries, report
+
+
+def Workload_table_op(op: str) -> int:
+    return {"copy": L.OP_COPY, "axpby": L.OP_AXPBY, "dot": L.OP_DOT, "nrm2": L.OP_NRM2, "cg": L.OP_CG}[op]
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the bwla kernels on this GPU")
+    ap.add_argument("--out", default=DEFAULT_TABLE, help="tuning table to write")
+    ap.add_argument("--report", default=None, help="JSON report to write")
+    ap.add_argument("--dtypes", default="f64,f32,bf16")
+    ap.add_argument("--quick", action="store_true", help="smaller candidate lists")
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    entries, report = tune_all(tuple(args.dtypes.split(",")), quick=args.quick,
+                               log=lambda *a: print(*a, flush=True))
+    _os.makedirs(_os.path.dirname(_os.path.abspath(args.out)), exist_ok=True)
+    write_table(entries, args.out)
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(report, f, indent=1)
+    print("wrote %s (%d entries) in %.0f s" % (args.out, len(entries), time.time() - t0), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,7 +143,7 @@ def test_load_tuning(L, tmp_path):
     p.write_text("1 0 -1 500 2 2 0 0 0 0\n")
     assert lib.bwla_load_tuning(str(p).encode()) == L.ERR_INVALID_ARG
     assert lib.bwla_load_tuning(b"/nonexistent/file") == L.ERR_INVALID_ARG
-    for op in range(6):
+    for op in range(L.OP_COUNT):
         for t in range(3):
             lib.bwla_set_config(op, t, -1, None)
 
@@ -177,7 +177,7 @@ def test_host_sizing_never_crashes_on_degenerate_shapes(L):
                         for op in (L.OP_GEMV_ROWS, L.OP_GEMV_COLS):
                             assert lib.bwla_workspace_size(op, t, 0, layout, trans, m, n, ctypes.byref(b)) == L.OK
                 assert lib.bwla_workspace_size(L.OP_DOT, t, 0, 0, 0, 0, n, ctypes.byref(b)) == L.OK
-                for op in range(6):
+                for op in range(L.OP_COUNT):
                     assert lib.bwla_get_config(op, t, m, n, ctypes.byref(c)) == L.OK
                     assert c.block >= 64 and c.vec >= 1 and c.split >= 1
 
