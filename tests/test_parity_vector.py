@@ -116,3 +116,28 @@ def test_axpby_empty_and_specials():
     ref = oracle.axpby("f64", 2.0, host(y), 0.0, host(z))
     assert bitwise_equal(x, ref)
     assert np.isnan(x[0])
+
+
+def test_axpby_and_dot_beyond_2_pow_31_elements():
+    """Indices past 2^31: bf16 vectors of 2^31 + 37 elements (4 GiB each),
+    axpby checked bitwise on sampled indices (including the tail) and dot
+    against the oracle on the same data."""
+    import workloads as W
+    from paper_1409_0669_amd import ops
+    n = (1 << 31) + 37
+    y = W.device_draw(n, "bf16", 0, 70)
+    z = W.device_draw(n, "bf16", 0, 71)
+    x = ops.axpby(ALPHA, y, BETA, z)
+    idx = np.concatenate([np.arange(8), np.random.default_rng(0).integers(0, n, 4096), np.arange(n - 64, n)])
+    ti = torch.from_numpy(idx).cuda()
+    y64, z64, x64 = host(y[ti]), host(z[ti]), host(x[ti])
+    ref = oracle.axpby("bf16", oracle.scalar("bf16", ALPHA), y64, oracle.scalar("bf16", BETA), z64)
+    assert bitwise_equal(x64, ref)
+    del x, y, z
+    # the reductions over all 2^31 + 37 elements: a closed form (every
+    # per-thread partial is an exactly representable count)
+    ones = torch.ones(n, dtype=torch.bfloat16, device="cuda")
+    assert float(ops.dot(ones, ones, out_dtype=torch.float64).item()) == n
+    assert float(ops.dot(ones, ones, acc="compensated", out_dtype=torch.float64).item()) == n
+    nr = float(ops.nrm2(ones, out_dtype=torch.float64).item())
+    assert abs(nr - np.sqrt(n)) <= 1e-12 * np.sqrt(n)
