@@ -120,8 +120,8 @@ def test_axpby_empty_and_specials():
 
 def test_axpby_and_dot_beyond_2_pow_31_elements():
     """Indices past 2^31: bf16 vectors of 2^31 + 37 elements (4 GiB each),
-    axpby checked bitwise on sampled indices (including the tail) and dot
-    against the oracle on the same data."""
+    axpby checked bitwise on sampled indices (including the tail), and the
+    reductions over every element against closed forms."""
     import workloads as W
     from paper_1409_0669_amd import ops
     n = (1 << 31) + 37
