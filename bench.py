@@ -195,6 +195,32 @@ def extra_rows(torch, W, ops, reps):
     return out
 
 
+def graph_step(torch, work, reps):
+    """The same 32-operation step captured once in a HIP graph and replayed:
+    the kernels are identical, launch overhead is removed."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            for _, _, fn in work:
+                fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _, _, fn in work:
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    step_bytes = sum(b for _, b, _ in work)
+    return {"GB/s": round(step_bytes / (ms * 1e-3) / 1e9, 1), "ms_per_step": round(ms, 4)}
+
+
 def cpu_baseline(W, oracle, seconds):
     """The oracle (plain single-threaded C) on a bounded sample of the same
     workload: the vector operations at n = 1e5, 1e6, 1e7 and the 4096 x 4096
@@ -328,6 +354,7 @@ def main():
     if not args.no_extra:
         log("timing the adjoint, reduced-precision and composite rows")
         extra = extra_rows(torch, W, ops, reps=max(5, args.steps))
+        extra["step via HIP graph replay"] = graph_step(torch, work, max(5, args.steps))
         if args.breakdown:
             for k, v in extra.items():
                 log("%-52s %s" % (k, v))

@@ -1,0 +1,48 @@
+"""bench.py: a one-step run prints one well-formed JSON line whose bytes per
+step equal the hand count of the minimal-bytes model (copy 2ns, axpby 3ns,
+dot 2ns, nrm2 ns, GEMV (mn + m + n) elements), and refuses more than one GPU."""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def hand_count():
+    total = 0
+    for s in (4, 8):
+        for n in (10 ** 5, 10 ** 6, 10 ** 7, 1 << 26):
+            total += (3 + 2 + 1) * n * s
+        for m in (4096, 16384):
+            total += 2 * (m * m + m + m) * s
+    return total
+
+
+def test_bench_refuses_several_gpus():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+
+
+@pytest.mark.gpu
+def test_bench_one_step_json():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "1", "--warmup", "1",
+                        "--no-extra", "--no-cpu-baseline"], capture_output=True, text=True, timeout=300)
+    assert p.returncode == 0, p.stderr[-2000:]
+    lines = [l for l in p.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["unit"] == "GB/s" and d["value"] > 0
+    assert d["config"]["bytes_per_step"] == hand_count()
+    r = d["roofline"]
+    assert r["bound"] == "hbm" and r["peak"] == 8000.0 and 0 < r["frac"] < 1.2
+    assert r["algorithmic_bytes"] == (16384 * 16384 + 2 * 16384) * 8

@@ -1,0 +1,87 @@
+"""The library's calls can be captured in a HIP graph (torch.cuda.CUDAGraph):
+they allocate nothing on the device and issue no memset or host
+synchronisation.  A captured sequence of every operation is replayed several
+times, with eager work and synchronisations between replays, and every replay
+must equal the eager results bitwise (all kernels are deterministic)."""
+from __future__ import annotations
+
+import pytest
+import torch
+
+import workloads as W
+from tests.criteria import bitwise_equal
+from tests.gpu_util import host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _build(dtype):
+    from paper_1409_0669_amd import ops
+    n = 300_017
+    y = W.device_draw(n, dtype, 0, 1)
+    z = W.device_draw(n, dtype, 0, 2)
+    A = W.device_draw(700 * 900, dtype, 0, 3).view(700, 900)
+    Ac = A.t().contiguous().t()
+    xv = W.device_draw(900, dtype, 0, 4)
+    xt = W.device_draw(700, dtype, 0, 5)
+    p = W.device_draw(n, dtype, 0, 6)
+    q = W.device_draw(n, dtype, 0, 7)
+    od = ops.default_out_dtype(y.dtype)
+    outs = {
+        "axpby": torch.empty_like(y), "dot": torch.empty((), dtype=od, device="cuda"),
+        "dotc": torch.empty((), dtype=od, device="cuda"), "nrm2": torch.empty((), dtype=od, device="cuda"),
+        "gr": torch.empty(700, dtype=od, device="cuda"), "gc": torch.empty(700, dtype=od, device="cuda"),
+        "gt": torch.empty(900, dtype=od, device="cuda"), "gct": torch.empty(900, dtype=od, device="cuda"),
+        "ger": torch.empty_like(A), "cg": torch.empty((), dtype=od, device="cuda"),
+    }
+    state = {"x": W.device_draw(n, dtype, 0, 8), "r": W.device_draw(n, dtype, 0, 9)}
+    init = {k: v.clone() for k, v in state.items()}
+
+    def step():
+        ops.axpby(0.75, y, -1.25, z, out=outs["axpby"])
+        ops.dot(y, z, out=outs["dot"])
+        ops.dot(y, z, acc="compensated", out=outs["dotc"])
+        ops.nrm2(y, out=outs["nrm2"])
+        ops.gemv(A, xv, out=outs["gr"])
+        ops.gemv(Ac, xv, out=outs["gc"])
+        ops.gemv(A, xt, trans=True, out=outs["gt"])
+        ops.gemv(Ac, xt, trans=True, out=outs["gct"])
+        ops.ger(xt, xv, outs["ger"])
+        state["x"].copy_(init["x"])
+        state["r"].copy_(init["r"])
+        ops.cg_update(0.01, state["x"], p, state["r"], q, out=outs["cg"])
+
+    return step, outs, state
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_graph_replay_equals_eager(dtype):
+    need_gpu()
+    step, outs, state = _build(dtype)
+    step()
+    torch.cuda.synchronize()
+    ref = {k: host(v) for k, v in outs.items()}
+    ref.update({k: host(v) for k, v in state.items()})
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):  # warm up on the side stream (workspaces for this stream)
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for v in outs.values():       # eager work between replays
+            v.fill_(float("nan") if v.is_floating_point() else 0)
+        for v in state.values():
+            v.fill_(3.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, v in outs.items():
+            assert bitwise_equal(host(v), ref[k]), (rep, k)
+        for k, v in state.items():
+            assert bitwise_equal(host(v), ref[k]), (rep, k)
