@@ -195,6 +195,63 @@ def extra_rows(torch, W, ops, reps):
     return out
 
 
+def uneven_batch_graph(torch, W, ops, dtype, reps):
+    """The uneven batch -- 512 row-major GEMVs with M, N log-uniform in
+    [32, 4096] and 4096 dots with n log-uniform in [1e3, 1e6] -- run as one
+    library call per problem, all captured in one HIP graph and replayed.
+    This is the baseline a persistent batched launch has to beat."""
+    M, N, D = W.batched_sizes(0)
+    s = 2 if dtype == "bf16" else 4
+    align = 64
+
+    def offsets(sizes):
+        o, offs = 0, []
+        for v in sizes:
+            offs.append(o)
+            o += (int(v) + align - 1) // align * align
+        return offs, max(o, 1)
+    a_off, a_tot = offsets(M * N)
+    x_off, x_tot = offsets(N)
+    d_off, d_tot = offsets(D)
+    A = W.device_draw(a_tot, dtype, 0, 501)
+    X = W.device_draw(x_tot, dtype, 0, 502)
+    P = W.device_draw(d_tot, dtype, 0, 503)
+    Q = W.device_draw(d_tot, dtype, 0, 504)
+    Y = torch.empty(int(M.sum()), dtype=torch.float32, device="cuda")
+    R = torch.empty(len(D), dtype=torch.float32, device="cuda")
+    calls, y0 = [], 0
+    for i, (m, n) in enumerate(zip(M, N)):
+        m, n = int(m), int(n)
+        Ai, xi, yi = A[a_off[i]:a_off[i] + m * n].view(m, n), X[x_off[i]:x_off[i] + n], Y[y0:y0 + m]
+        calls.append(lambda Ai=Ai, xi=xi, yi=yi: ops.gemv(Ai, xi, acc="compensated", out=yi))
+        y0 += m
+    for i, n in enumerate(D):
+        n = int(n)
+        pi, qi, ri = P[d_off[i]:d_off[i] + n], Q[d_off[i]:d_off[i] + n], R[i:i + 1]
+        calls.append(lambda pi=pi, qi=qi, ri=ri: ops.dot(pi, qi, acc="compensated", out=ri.view(())))
+    nbytes = float(((M * N + M + N) * s).sum() + (2 * D * s).sum() + 4 * (M.sum() + len(D)))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for c in calls:
+            c()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for c in calls:
+            c()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 3), "problems": len(calls),
+            "bytes": int(nbytes)}
+
+
 def graph_step(torch, work, reps):
     """The same 32-operation step captured once in a HIP graph and replayed:
     the kernels are identical, launch overhead is removed."""
@@ -355,6 +412,9 @@ def main():
         log("timing the adjoint, reduced-precision and composite rows")
         extra = extra_rows(torch, W, ops, reps=max(5, args.steps))
         extra["step via HIP graph replay"] = graph_step(torch, work, max(5, args.steps))
+        for dt in ("bf16", "f32"):
+            extra["uneven batch %s, compensated, per-problem calls in one HIP graph" % dt] = \
+                uneven_batch_graph(torch, W, ops, dt, 5)
         if args.breakdown:
             for k, v in extra.items():
                 log("%-52s %s" % (k, v))

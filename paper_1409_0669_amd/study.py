@@ -1,0 +1,138 @@
+"""The paper's configuration study repeated on gfx950 (Sections 3.1-3.4).
+
+For copy, scaled addition, inner product and norm at the paper's vector size
+(two million float64 entries; Section 3) and at 2^26 entries (beyond the
+256 MB Infinity Cache), every configuration of the gfx950 space
+(``tune.vector_space``: work-group size 64-1024, vector width 1-16, unroll
+1-4, increment global/local, work-groups per CU 1-32 or one pass) is timed.
+The report gives:
+
+* per-parameter distributions for the inner product (the paper's Figures
+  1-4: increment type, vector type, local work size, number of work-groups),
+  as quantiles of the fraction of peak bandwidth;
+* the copy-vs-operation relation across configurations (Figure 5): rank
+  correlation, and the best operation rate among configurations whose copy
+  rate is within 5 % of the best copy;
+* the single-configuration comparison (Table 2): every operation run with the
+  copy's best configuration against its own best.
+
+Run on the GPU: ``python -m paper_1409_0669_amd.study --json OUT.json --md OUT.md``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import statistics
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import ops, tune
+
+PEAK_GBS = 8000.0
+OPS = ("copy", "axpby", "dot", "nrm2")
+
+
+def _key(c):
+    return tuple(sorted(c.items()))
+
+
+def run(sizes=(2_000_000, 1 << 26), dtype=torch.float64, reps=5, log=print):
+    cus = L.lib.bwla_device_cus()
+    space = tune.vector_space(cus)
+    ops.reset_config()
+    out = {"device": torch.cuda.get_device_name(), "cus": cus, "configs": len(space), "sizes": {}}
+    for n in sizes:
+        rates = {}
+        for op in OPS:
+            w = tune.Workload(op, dtype, n=n)
+            t0 = time.time()
+            res = tune.sweep(w, space, reps=reps)
+            rates[op] = {_key(c): g for c, _, g in res}
+            log("n=%d %-5s %d configs in %.0f s, best %.1f GB/s" % (n, op, len(res), time.time() - t0, res[0][2]))
+            del w
+        out["sizes"][str(n)] = analyse(space, rates)
+    ops.reset_config()
+    return out
+
+
+def analyse(space, rates):
+    keys = [k for k in (_key(c) for c in space) if all(k in rates[op] for op in OPS)]
+    frac = {op: np.array([rates[op][k] / PEAK_GBS for k in keys]) for op in OPS}
+    cfgs = [dict(k) for k in keys]
+    rep = {"n_configs": len(keys)}
+    # Figures 1-4: distributions of the inner product per parameter value
+    dist = {}
+    for param in ("increment", "vec", "block", "grid"):
+        d = {}
+        for v in sorted({c[param] for c in cfgs}):
+            sel = np.array([c[param] == v for c in cfgs])
+            vals = frac["dot"][sel]
+            d[str(v)] = {"median": round(float(np.median(vals)), 3), "p90": round(float(np.quantile(vals, 0.9)), 3),
+                         "max": round(float(vals.max()), 3), "n": int(sel.sum())}
+        dist[param] = d
+    rep["dot_distributions"] = dist
+    # Figure 5: copy against the other operations
+    def ranks(a):
+        r = np.empty(len(a))
+        r[np.argsort(a)] = np.arange(len(a))
+        return r
+    best_copy = frac["copy"].max()
+    near = frac["copy"] >= 0.95 * best_copy
+    rel = {}
+    for op in OPS[1:]:
+        rho = float(np.corrcoef(ranks(frac["copy"]), ranks(frac[op]))[0, 1])
+        rel[op] = {"spearman_rho": round(rho, 3), "best": round(float(frac[op].max()), 3),
+                   "best_among_near_copy_best": round(float(frac[op][near].max()), 3),
+                   "near_copy_best_configs": int(near.sum())}
+    rep["copy_vs_ops"] = rel
+    # Table 2: the copy's best configuration for every operation
+    i = int(np.argmax(frac["copy"]))
+    rep["table2"] = {"config": cfgs[i], **{op: {"with_copy_cfg": round(float(frac[op][i]), 3),
+                                                 "own_best": round(float(frac[op].max()), 3),
+                                                 "own_best_config": cfgs[int(np.argmax(frac[op]))]}
+                                           for op in OPS}}
+    return rep
+
+
+def markdown(res) -> str:
+    lines = ["# The paper's configuration study on %s (%d CUs)" % (res["device"], res["cus"]), "",
+             "%d configurations per operation, float64, fraction of the 8 TB/s HBM peak." % res["configs"], ""]
+    for n, r in res["sizes"].items():
+        lines += ["## n = %s" % n, "", "Single configuration chosen by the copy (Table 2 analogue): `%s`" % r["table2"]["config"], "",
+                  "| operation | with the copy's config | own best | penalty |", "|---|---|---|---|"]
+        for op in OPS:
+            t = r["table2"][op]
+            lines.append("| %s | %.3f | %.3f | %.1f %% |" % (op, t["with_copy_cfg"], t["own_best"],
+                                                          100 * (1 - t["with_copy_cfg"] / t["own_best"])))
+        lines += ["", "Copy vs the other operations across all configurations (Figure 5 analogue):", "",
+                  "| operation | Spearman rho | best | best among configs within 5 % of the best copy |", "|---|---|---|---|"]
+        for op, v in r["copy_vs_ops"].items():
+            lines.append("| %s | %.3f | %.3f | %.3f (%d configs) |" % (op, v["spearman_rho"], v["best"],
+                                                                      v["best_among_near_copy_best"], v["near_copy_best_configs"]))
+        lines += ["", "Inner product by parameter (Figures 1-4 analogue): median / 90th percentile / max fraction of peak", ""]
+        for p, d in r["dot_distributions"].items():
+            lines.append("- **%s**: " % p + "; ".join("%s: %.2f/%.2f/%.2f" % (k, v["median"], v["p90"], v["max"])
+                                                    for k, v in d.items()))
+        lines.append("")
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--json", required=True)
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    res = run(reps=args.reps, log=lambda *a: print(*a, flush=True))
+    with open(args.json, "w") as f:
+        json.dump(res, f, indent=1)
+    with open(args.md, "w") as f:
+        f.write(markdown(res))
+    print(markdown(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -85,3 +85,62 @@ def test_graph_replay_equals_eager(dtype):
             assert bitwise_equal(host(v), ref[k]), (rep, k)
         for k, v in state.items():
             assert bitwise_equal(host(v), ref[k]), (rep, k)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_uneven_batch_as_graph_of_calls(dtype):
+    """Many uneven GEMVs and dots issued as individual library calls captured
+    in one graph (the baseline for a persistent batched launch): sampled
+    problems match the oracle, and a second replay is bitwise identical."""
+    need_gpu()
+    import numpy as np
+    import oracle
+    from paper_1409_0669_amd import ops
+    from tests.criteria import TOL, check_scalar, check_vector
+    rng = np.random.default_rng(5)
+    M = W.loguniform_sizes(32, 1500, 48, 0, 1)
+    N = W.loguniform_sizes(32, 1500, 48, 0, 2)
+    D = W.loguniform_sizes(1000, 300_000, 200, 0, 3)
+    gem, dots = [], []
+    for i, (m, n) in enumerate(zip(M, N)):
+        A = W.device_draw(int(m) * int(n), dtype, 1, 100 + i).view(int(m), int(n))
+        x = W.device_draw(int(n), dtype, 1, 300 + i)
+        gem.append((A, x, torch.empty(int(m), dtype=torch.float32, device="cuda")))
+    for i, n in enumerate(D):
+        dots.append((W.device_draw(int(n), dtype, 1, 500 + i), W.device_draw(int(n), dtype, 1, 900 + i),
+                     torch.empty((), dtype=torch.float32, device="cuda")))
+
+    def run():
+        for A, x, y in gem:
+            ops.gemv(A, x, acc="compensated", out=y)
+        for p, q, o in dots:
+            ops.dot(p, q, acc="compensated", out=o)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    g.replay()
+    torch.cuda.synchronize()
+    first = [host(y) for _, _, y in gem] + [host(o) for _, _, o in dots]
+    for i in rng.choice(len(gem), 10, replace=False):
+        A, x, y = gem[i]
+        A64, x64 = host(A), host(x)
+        check_vector(first[i], oracle.gemv(A64, x64), np.abs(A64) @ np.abs(x64), TOL[dtype])
+    for i in rng.choice(len(dots), 20, replace=False):
+        p, q, o = dots[i]
+        p64, q64 = host(p), host(q)
+        check_scalar(float(first[len(gem) + i]), oracle.dot(p64, q64), float(np.abs(p64 * q64).sum()), TOL[dtype])
+    for _, _, y in gem:
+        y.fill_(float("nan"))
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    again = [host(y) for _, _, y in gem] + [host(o) for _, _, o in dots]
+    for a, b in zip(first, again):
+        assert bitwise_equal(a, b)

@@ -61,3 +61,24 @@ def test_write_table_roundtrip(tmp_path):
     L.lib.bwla_get_config(L.OP_AXPBY, L.F32, 0, 1 << 26, ctypes.byref(c))
     assert (c.block, c.vec, c.unroll, c.grid, c.increment) == (512, 8, 2, 2048, 1)
     L.lib.bwla_set_config(L.OP_AXPBY, L.F32, -1, None)
+
+
+def test_study_analysis_on_synthetic_rates():
+    """The configuration-study analysis: when every operation's rate is a fixed
+    multiple of the copy's, the rank correlation is 1 and the copy's best
+    configuration is every operation's best (no Table 2 penalty)."""
+    import numpy as np
+    from paper_1409_0669_amd import study, tune
+    space = tune.vector_space(256)
+    rng = np.random.default_rng(1)
+    base = {study._key(c): float(rng.uniform(1000, 7000)) for c in space}
+    rates = {op: {k: v * f for k, v in base.items()} for op, f in zip(study.OPS, (1.0, 0.9, 0.95, 0.8))}
+    r = study.analyse(space, rates)
+    assert r["n_configs"] == len(space)
+    for op in study.OPS[1:]:
+        assert abs(r["copy_vs_ops"][op]["spearman_rho"] - 1.0) < 1e-9
+    for op in study.OPS:
+        assert r["table2"][op]["with_copy_cfg"] == r["table2"][op]["own_best"]
+    assert set(r["dot_distributions"]) == {"increment", "vec", "block", "grid"}
+    md = study.markdown({"device": "synthetic", "cus": 256, "configs": len(space), "sizes": {"2000000": r}})
+    assert "Table 2" in md and "Spearman" in md
