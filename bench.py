@@ -191,15 +191,13 @@ def extra_rows(torch, W, ops, reps):
     q = torch.empty(m, dtype=torch.float64, device="cuda")
     rate("composite gemv 8192^2 + dot f64", (m * m + 3 * m) * 8, lambda: composite.gemv_dot(A, pv, q=q))
     del A
-    out["batched"] = "not measured: the persistent batched kernel is disabled until validated on hardware"
     return out
 
 
-def uneven_batch_graph(torch, W, ops, dtype, reps):
-    """The uneven batch -- 512 row-major GEMVs with M, N log-uniform in
-    [32, 4096] and 4096 dots with n log-uniform in [1e3, 1e6] -- run as one
-    library call per problem, all captured in one HIP graph and replayed.
-    This is the baseline a persistent batched launch has to beat."""
+def uneven_batch(torch, W, ops, dtype):
+    """The uneven batch: 512 row-major GEMVs with M, N log-uniform in
+    [32, 4096] and 4096 dots with n log-uniform in [1e3, 1e6] (float32
+    outputs).  Returns (gemvs, dots, algorithmic bytes)."""
     M, N, D = W.batched_sizes(0)
     s = 2 if dtype == "bf16" else 4
     align = 64
@@ -219,37 +217,74 @@ def uneven_batch_graph(torch, W, ops, dtype, reps):
     Q = W.device_draw(d_tot, dtype, 0, 504)
     Y = torch.empty(int(M.sum()), dtype=torch.float32, device="cuda")
     R = torch.empty(len(D), dtype=torch.float32, device="cuda")
-    calls, y0 = [], 0
+    gemvs, dots, y0 = [], [], 0
     for i, (m, n) in enumerate(zip(M, N)):
         m, n = int(m), int(n)
-        Ai, xi, yi = A[a_off[i]:a_off[i] + m * n].view(m, n), X[x_off[i]:x_off[i] + n], Y[y0:y0 + m]
-        calls.append(lambda Ai=Ai, xi=xi, yi=yi: ops.gemv(Ai, xi, acc="compensated", out=yi))
+        gemvs.append((A[a_off[i]:a_off[i] + m * n].view(m, n), X[x_off[i]:x_off[i] + n], Y[y0:y0 + m]))
         y0 += m
     for i, n in enumerate(D):
         n = int(n)
-        pi, qi, ri = P[d_off[i]:d_off[i] + n], Q[d_off[i]:d_off[i] + n], R[i:i + 1]
-        calls.append(lambda pi=pi, qi=qi, ri=ri: ops.dot(pi, qi, acc="compensated", out=ri.view(())))
+        dots.append((P[d_off[i]:d_off[i] + n], Q[d_off[i]:d_off[i] + n], R[i:i + 1]))
     nbytes = float(((M * N + M + N) * s).sum() + (2 * D * s).sum() + 4 * (M.sum() + len(D)))
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        for c in calls:
-            c()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        for c in calls:
-            c()
+    return gemvs, dots, nbytes
+
+
+def _replay_ms(torch, g, reps):
     g.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         g.replay()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / reps
-    return {"GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 3), "problems": len(calls),
-            "bytes": int(nbytes)}
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def batched_rows(torch, W, ops, reps):
+    """The uneven batch three ways: the batched plan (one launch, one
+    work-group per work item) launched directly and replayed from its HIP
+    graph, and -- as the baseline it replaces -- one library call per problem,
+    all captured in one HIP graph."""
+    from paper_1409_0669_amd.batch import BatchPlan
+    out = {}
+    for dt in ("bf16", "f32"):
+        gemvs, dots, nbytes = uneven_batch(torch, W, ops, dt)
+        plan = BatchPlan(gemvs, [(p, q, r) for p, q, r in dots], acc="compensated")
+        ms = _median_ms(torch, plan.run, reps)
+        info = plan.info()
+        out["batched %s compensated, one launch (%d items)" % (dt, info["items"])] = {
+            "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 3), "bytes": int(nbytes)}
+        cap = torch.cuda.Stream()
+        plan.capture(cap)
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.replay()
+            e1.record()
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1))
+        t.sort()
+        out["batched %s compensated, plan graph replay" % dt] = {
+            "GB/s": round(nbytes / (t[len(t) // 2] * 1e-3) / 1e9, 1), "ms": round(t[len(t) // 2], 3)}
+        calls = [lambda A=A, x=x, y=y: ops.gemv(A, x, acc="compensated", out=y) for A, x, y in gemvs]
+        calls += [lambda p=p, q=q, r=r: ops.dot(p, q, acc="compensated", out=r.view(())) for p, q, r in dots]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for c in calls:
+                c()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for c in calls:
+                c()
+        ms = _replay_ms(torch, g, max(3, reps // 2))
+        out["baseline %s: %d per-problem calls in one HIP graph" % (dt, len(calls))] = {
+            "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 3)}
+        plan.close()
+        del gemvs, dots, g
+    return out
 
 
 def graph_step(torch, work, reps):
@@ -412,9 +447,7 @@ def main():
         log("timing the adjoint, reduced-precision and composite rows")
         extra = extra_rows(torch, W, ops, reps=max(5, args.steps))
         extra["step via HIP graph replay"] = graph_step(torch, work, max(5, args.steps))
-        for dt in ("bf16", "f32"):
-            extra["uneven batch %s, compensated, per-problem calls in one HIP graph" % dt] = \
-                uneven_batch_graph(torch, W, ops, dt, 5)
+        extra.update(batched_rows(torch, W, ops, max(5, args.steps // 2)))
         if args.breakdown:
             for k, v in extra.items():
                 log("%-52s %s" % (k, v))

@@ -178,21 +178,21 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
 /* ---- batched uneven problems in one persistent launch -------------------
  * A plan holds many row-major GEMVs (y = A x, out_t output) and many dots
  * (out = <x, y>, out_t output) of one storage type.  Work is flattened into
- * items (row tiles of a GEMV, chunks of a dot) ordered largest first; a
- * persistent grid takes items from an atomic counter.  Each dot's chunk
- * partials are combined in chunk order by a finalize kernel, so results do
- * not depend on the batch order or on scheduling.
+ * items (row tiles of a GEMV, chunks of a dot) ordered largest first and run
+ * in one launch with one work-group per item (the hardware dispatcher hands
+ * out the items in order).  Each dot's chunk partials are combined in chunk
+ * order by a finalize kernel, so results do not depend on the batch order or
+ * on scheduling.
  * create: copies the descriptors to the device and allocates the plan's own
  *         counters and partial slots (the only allocating call; not allowed
  *         while `stream` capture is active).
- * run:    enqueues the counter reset, the persistent kernel and the dot
- *         finalize kernel.
- * capture: records the same three kernels into a HIP graph owned by the plan.
+ * run:    enqueues the batched kernel and the dot finalize kernel.
+ * capture: records the same kernels into a HIP graph owned by the plan.
  * replay: launches the captured graph.
  * Descriptor pointers must stay valid while the plan is used.
- * Status: run and capture return BWLA_ERR_UNSUPPORTED unless the environment
- * variable BWLA_ENABLE_UNVALIDATED_BATCH=1 is set: the persistent kernel's
- * current form has not yet been validated on hardware. */
+ * A persistent work-queue kernel (a machine-sized grid drawing items from an
+ * atomic counter) is used instead when BWLA_ENABLE_UNVALIDATED_BATCH=1 is set
+ * at plan creation; its current form has not been validated on hardware. */
 typedef struct bwla_batch_plan bwla_batch_plan;
 typedef struct {
     const void *A;

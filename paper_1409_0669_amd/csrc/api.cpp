@@ -728,6 +728,7 @@ bwla_status bwla_load_tuning(const char *path)
 // ===========================================================================
 struct bwla_batch_plan {
     int t = 0, acc = 0, out_t = 0;
+    bool persistent = false; // persistent work-queue kernel (opt-in) or grouped launch
     int device = 0;
     int grid = 0, block = 256, vec = 1;
     int64_t n_items = 0, n_dots = 0;
@@ -758,22 +759,27 @@ void plan_free(bwla_batch_plan *p)
     delete p;
 }
 
-// The persistent batched kernel hung on hardware twice (a compiler-divergent
-// loop around its work draw; see batched.hip) and its corrected form has not
-// yet been run on a GPU.  Until it has, launching it is opt-in.
-bool batch_launch_enabled()
+// Plans use the grouped launch (one work-group per item).  The persistent
+// work-queue kernel hung on hardware twice (a compiler-divergent loop around
+// its work draw; see batched.hip) and its corrected form has not been run on
+// a GPU yet, so plans use it only when BWLA_ENABLE_UNVALIDATED_BATCH=1 is set
+// at plan creation.
+bool persistent_requested()
 {
     const char *v = getenv("BWLA_ENABLE_UNVALIDATED_BATCH");
     return v && v[0] == '1';
 }
-const char *kBatchDisabled = "the batched persistent kernel is disabled until it is validated on hardware "
-                             "(set BWLA_ENABLE_UNVALIDATED_BATCH=1 to launch it anyway)";
 
 hipError_t enqueue_batch(bwla_batch_plan *p, hipStream_t s)
 {
-    hipError_t e = launch_batch_reset(p->d_counters, 1, s);
-    if (e != hipSuccess)
-        return e;
+    hipError_t e = hipSuccess;
+    if (p->n_items == 0)
+        return e; // nothing to compute
+    if (p->persistent) {
+        e = launch_batch_reset(p->d_counters, 1, s);
+        if (e != hipSuccess)
+            return e;
+    }
     BatchArgs a;
     a.items = p->d_items;
     a.n_items = p->n_items;
@@ -785,7 +791,9 @@ hipError_t enqueue_batch(bwla_batch_plan *p, hipStream_t s)
     a.vec = p->vec;
     e = by_type(p->t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
-        return launch_batched<T>(a, p->acc == BWLA_ACC_COMPENSATED, p->grid, p->block, s);
+        if (p->persistent)
+            return launch_batched<T>(a, p->acc == BWLA_ACC_COMPENSATED, p->grid, p->block, s);
+        return launch_grouped<T>(a, p->acc == BWLA_ACC_COMPENSATED, p->block, s);
     });
     if (e != hipSuccess)
         return e;
@@ -851,6 +859,7 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
     p->out_t = out_t;
     p->vec = aligned ? nv : 1;
     p->block = cfg && cfg->block ? cfg->block : 256;
+    p->persistent = persistent_requested();
     (void)hipGetDevice(&p->device);
 
     // work items, with their cost in bytes for the largest-first order
@@ -861,9 +870,11 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
     std::vector<Work> work;
     std::vector<BatchGemv> hg(ng);
     std::vector<BatchDot> hd(nd);
-    // Work items are sized for one wave64 each.
-    const int64_t kTileElems = 1 << 15; // elements of A per GEMV row tile
-    const int64_t kChunk = 1 << 14;     // elements per dot chunk (a multiple of 64*vec)
+    // Work items: sized for one wave64 each in the persistent kernel, for one
+    // work-group each in the grouped launch.  Chunk starts stay multiples of
+    // 64 * 16 elements, so every chunk begins on a pack boundary.
+    const int64_t kTileElems = p->persistent ? (1 << 15) : (1 << 16); // elements of A per GEMV row tile
+    const int64_t kChunk = p->persistent ? (1 << 14) : (1 << 16);     // elements per dot chunk
     for (int i = 0; i < ng; ++i) {
         const bwla_gemv_desc &q = g[i];
         BatchGemv &b = hg[i];
@@ -923,13 +934,21 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         items[i] = work[i].it;
     p->n_items = (int64_t)items.size();
     p->n_dots = nd;
-    // One wave per item at a time: enough work-groups to fill every CU's wave
-    // slots, but no more waves than items.
-    const int64_t per_cu = std::max(1, 2048 / p->block);
-    const int64_t waves_per_block = p->block / 64;
-    int64_t grid = cfg && cfg->grid ? cfg->grid : (int64_t)device_cus() * per_cu;
-    grid = std::min<int64_t>(grid, ceil_div(std::max<int64_t>(1, p->n_items), waves_per_block));
-    p->grid = (int)std::max<int64_t>(1, grid);
+    if (p->n_items > 0x7fffffff) {
+        delete p;
+        return fail(BWLA_ERR_INVALID_ARG, "batch has more than 2^31 - 1 work items");
+    }
+    if (p->persistent) {
+        // One wave per item at a time: enough work-groups to fill every CU's
+        // wave slots, but no more waves than items.
+        const int64_t per_cu = std::max(1, 2048 / p->block);
+        const int64_t waves_per_block = p->block / 64;
+        int64_t grid = cfg && cfg->grid ? cfg->grid : (int64_t)device_cus() * per_cu;
+        grid = std::min<int64_t>(grid, ceil_div(std::max<int64_t>(1, p->n_items), waves_per_block));
+        p->grid = (int)std::max<int64_t>(1, grid);
+    } else {
+        p->grid = (int)std::max<int64_t>(1, p->n_items); // one work-group per item
+    }
 
     auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
         if (bytes == 0)
@@ -966,8 +985,8 @@ bwla_status bwla_batch_run(bwla_batch_plan *p, void *stream)
 {
     if (!p)
         return fail(BWLA_ERR_INVALID_ARG, "plan is NULL");
-    if (!batch_launch_enabled())
-        return fail(BWLA_ERR_UNSUPPORTED, "%s", kBatchDisabled);
+    if (p->n_items == 0)
+        return BWLA_OK;
     return hip_check(enqueue_batch(p, (hipStream_t)stream), "batched launch");
 }
 
@@ -975,8 +994,6 @@ bwla_status bwla_batch_capture(bwla_batch_plan *p, void *stream)
 {
     if (!p)
         return fail(BWLA_ERR_INVALID_ARG, "plan is NULL");
-    if (!batch_launch_enabled())
-        return fail(BWLA_ERR_UNSUPPORTED, "%s", kBatchDisabled);
     hipStream_t s = (hipStream_t)stream;
     if (!s)
         return fail(BWLA_ERR_NOT_CAPTURABLE, "the default stream cannot be captured; pass a created stream");

@@ -1,4 +1,10 @@
-// batched.hip -- many uneven row-major GEMVs and dots in one persistent launch.
+// batched.hip -- many uneven row-major GEMVs and dots in one launch.
+//
+// Two designs share the work-item list.  The grouped launch (k_grouped,
+// below the persistent kernel) runs one work-group per item.  The
+// persistent kernel (k_batched) keeps a grid sized to the machine busy from
+// an atomic work queue; it is launched only on explicit opt-in (see the
+// plan code in api.cpp).
 //
 // The host flattens every problem into work items -- row tiles of a GEMV
 // (full row length) and fixed-size chunks of a dot -- ordered by decreasing
@@ -112,6 +118,98 @@ __global__ __launch_bounds__(1024) void k_batched(BatchArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Grouped launch: one work-group per work item, no work queue.  Items are
+// ordered largest first and the hardware dispatcher hands work-groups to CUs
+// in index order as they free up, which schedules the items the way a
+// largest-first queue would -- without a software loop over items, without
+// atomics, and with barriers only in straight-line code.
+// ---------------------------------------------------------------------------
+template <typename T, int V, bool COMP>
+__device__ __forceinline__ void gemv_tile_block(const BatchGemv &g, int64_t rb, int64_t re, int out_f64)
+{
+    using C = compute_t<T>;
+    constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int G = g.lanes;
+    const int rpw = 64 / G;
+    const int sub = lane / G, gl = lane - sub * G;
+    const T *A = (const T *)g.A;
+    const T *x = (const T *)g.x;
+    const int64_t K = g.n, kpack = K / V;
+    for (int64_t base = rb + (int64_t)wave * rpw; base < re; base += (int64_t)nw * rpw) {
+        const int64_t r = base + sub;
+        const int64_t rr = r < re ? r : re - 1;
+        const T *row = A + rr * g.lda;
+        Acc<C, COMP> acc;
+        for (int64_t p = gl; p < kpack; p += G) {
+            Pack<T, V> av = load_pack_nt<T, V>(row + p * V), xv = load_pack<T, V>(x + p * V);
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                acc.template add_prod<EXACT>(widen(av.v[e]), widen(xv.v[e]));
+        }
+        for (int64_t k = kpack * V + gl; k < K; k += G)
+            acc.template add_prod<EXACT>(widen(row[k]), widen(x[k]));
+        DD d = acc.to_dd();
+        for (int m = G >> 1; m >= 1; m >>= 1)
+            d = combine<COMP>(d, shfl_xor_dd(d, m));
+        if (gl == 0 && r < re)
+            store_out(g.y, r, out_f64, d.hi + d.lo);
+    }
+}
+
+template <typename T, int V, bool COMP>
+__device__ __forceinline__ void dot_chunk_block(const BatchArgs &a, const BatchItem &w, DD *lds)
+{
+    using C = compute_t<T>;
+    constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    const BatchDot &d = a.dots[w.prob];
+    const T *x = (const T *)d.x, *y = (const T *)d.y;
+    Acc<C, COMP> acc[2];
+    const int64_t pb = w.begin / V, pe = w.end / V; // chunk starts are pack-aligned
+    int64_t p = pb + threadIdx.x;
+    for (; p + blockDim.x < pe; p += 2 * (int64_t)blockDim.x) {
+        Pack<T, V> x0 = load_pack_nt<T, V>(x + p * V), y0 = load_pack_nt<T, V>(y + p * V);
+        Pack<T, V> x1 = load_pack_nt<T, V>(x + (p + blockDim.x) * V);
+        Pack<T, V> y1 = load_pack_nt<T, V>(y + (p + blockDim.x) * V);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            acc[0].template add_prod<EXACT>(widen(x0.v[e]), widen(y0.v[e]));
+            acc[1].template add_prod<EXACT>(widen(x1.v[e]), widen(y1.v[e]));
+        }
+    }
+    for (; p < pe; p += blockDim.x) {
+        Pack<T, V> x0 = load_pack_nt<T, V>(x + p * V), y0 = load_pack_nt<T, V>(y + p * V);
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            acc[0].template add_prod<EXACT>(widen(x0.v[e]), widen(y0.v[e]));
+    }
+    const int64_t tail = w.end - pe * V; // < V, only in a dot's last chunk
+    if (threadIdx.x < tail)
+        acc[0].template add_prod<EXACT>(widen(x[pe * V + threadIdx.x]), widen(y[pe * V + threadIdx.x]));
+    DD v = block_sum<COMP>(combine<COMP>(acc[0].to_dd(), acc[1].to_dd()), lds);
+    if (threadIdx.x == 0) {
+        if (d.chunks == 1)
+            store_out(d.out, 0, a.out_f64, v.hi + v.lo);
+        else
+            reinterpret_cast<DD *>(a.partials)[d.slot0 + w.chunk] = v;
+    }
+}
+
+template <typename T, int V, bool COMP>
+__global__ __launch_bounds__(1024) void k_grouped(BatchArgs a)
+{
+    __shared__ DD lds[16];
+    const BatchItem w = a.items[blockIdx.x];
+    // the item is the same for every thread of the work-group; readfirstlane
+    // makes the branch visibly uniform (block_sum below holds barriers)
+    const int kind = __builtin_amdgcn_readfirstlane(w.kind);
+    if (kind == 0)
+        gemv_tile_block<T, V, COMP>(a.gemv[w.prob], w.begin, w.end, a.out_f64);
+    else
+        dot_chunk_block<T, V, COMP>(a, w, lds);
+}
+
 #if BWLA_T_IS_F64 // type-independent kernels live in the f64 object only
 __global__ void k_zero_counters(unsigned *c, int64_t count)
 {
@@ -156,6 +254,23 @@ hipError_t launch_batched(const BatchArgs &a, bool comp, int grid, int block, hi
 }
 
 template hipError_t launch_batched<BWLA_T>(const BatchArgs &, bool, int, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_grouped(const BatchArgs &a, bool comp, int block, hipStream_t s)
+{
+    constexpr int NATIVE = 16 / (int)sizeof(T);
+    auto go = [&](auto V) {
+        return with_bool(comp, [&](auto CP) {
+            hipLaunchKernelGGL((k_grouped<T, V.value, CP.value>), dim3((unsigned)a.n_items), dim3(block), 0, s, a);
+            return hipGetLastError();
+        });
+    };
+    if (a.vec == 1)
+        return go(std::integral_constant<int, 1>{});
+    return go(std::integral_constant<int, NATIVE>{});
+}
+
+template hipError_t launch_grouped<BWLA_T>(const BatchArgs &, bool, int, hipStream_t);
 
 #if BWLA_T_IS_F64
 hipError_t launch_batch_reset(unsigned *counters, int64_t count, hipStream_t s)

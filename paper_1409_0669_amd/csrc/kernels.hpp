@@ -139,6 +139,9 @@ struct BatchArgs {
 template <typename T>
 hipError_t launch_batched(const BatchArgs &a, bool comp, int grid, int block, hipStream_t s);
 hipError_t launch_batch_reset(unsigned *counters, int64_t count, hipStream_t s);
+// One work-group per item (a.n_items work-groups of `block` threads).
+template <typename T>
+hipError_t launch_grouped(const BatchArgs &a, bool comp, int block, hipStream_t s);
 // Combines the chunk partials of every multi-chunk dot, in chunk order.
 hipError_t launch_batch_finalize(const BatchDot *dots, int64_t nd, const double *partials, bool comp,
                                  int out_f64, hipStream_t s);

@@ -1,6 +1,8 @@
-"""Batched persistent launch: every problem matches the oracle; results are
-bitwise independent of the batch order; graph replays equal the direct launch
-bitwise; a batch of one matches the single-problem call."""
+"""Batched launch with the persistent work-queue kernel: every problem
+matches the oracle; results are bitwise independent of the batch order; graph
+replays equal the direct launch bitwise; a batch of one matches the
+single-problem call.  The persistent kernel is selected with
+BWLA_ENABLE_UNVALIDATED_BATCH=1 at plan creation."""
 from __future__ import annotations
 
 import numpy as np
@@ -9,6 +11,7 @@ import torch
 
 import oracle
 import workloads as W
+from tests.batch_util import check, from_sizes, problems
 from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector
 from tests.gpu_util import DT, host, need_gpu
 
@@ -20,56 +23,9 @@ pytestmark = [
 ]
 
 
-def _problems(dtype, n_gemv, n_dot, gemv_hi, dot_hi, seed=0, align=64):
-    """Device buffers sliced into uneven problems (starts aligned to `align`
-    elements) and the host float64 copies."""
-    rng = np.random.default_rng(seed)
-    Ms = rng.integers(1, gemv_hi + 1, n_gemv)
-    Ns = rng.integers(1, gemv_hi + 1, n_gemv)
-    Ds = rng.integers(0, dot_hi + 1, n_dot)
-    return _from_sizes(dtype, Ms, Ns, Ds, seed, align)
-
-
-def _from_sizes(dtype, Ms, Ns, Ds, seed=0, align=64):
-    def off(sizes):
-        o, offs = 0, []
-        for s in sizes:
-            offs.append(o)
-            o += (int(s) + align - 1) // align * align
-        return offs, max(o, 1)
-    a_off, a_tot = off(Ms * Ns)
-    x_off, x_tot = off(Ns)
-    d_off, d_tot = off(Ds)
-    A = W.device_draw(a_tot, dtype, seed, 501)
-    X = W.device_draw(x_tot, dtype, seed, 502)
-    P = W.device_draw(d_tot, dtype, seed, 503)
-    Q = W.device_draw(d_tot, dtype, seed, 504)
-    od = torch.float64 if dtype == "f64" else torch.float32
-    gemvs = []
-    for i, (m, n) in enumerate(zip(Ms, Ns)):
-        m, n = int(m), int(n)
-        Ai = A[a_off[i]:a_off[i] + m * n].view(m, n)
-        xi = X[x_off[i]:x_off[i] + n]
-        gemvs.append((Ai, xi, torch.empty(m, dtype=od, device="cuda")))
-    dots = []
-    for i, n in enumerate(Ds):
-        n = int(n)
-        dots.append((P[d_off[i]:d_off[i] + n], Q[d_off[i]:d_off[i] + n], torch.empty(1, dtype=od, device="cuda")))
-    return gemvs, dots
-
-
-def _check(dtype, gemvs, dots, gi=None, di=None):
-    gi = range(len(gemvs)) if gi is None else gi
-    di = range(len(dots)) if di is None else di
-    for i in gi:
-        A, x, y = gemvs[i]
-        A64, x64 = host(A), host(x)
-        ref = oracle.gemv(A64, x64)
-        check_vector(host(y), ref, np.abs(A64) @ np.abs(x64), TOL[dtype], "gemv %d" % i)
-    for i in di:
-        p, q, out = dots[i]
-        p64, q64 = host(p), host(q)
-        check_scalar(float(out.item()), oracle.dot(p64, q64), float(np.abs(p64 * q64).sum()), TOL[dtype], "dot %d" % i)
+@pytest.fixture(autouse=True)
+def _persistent(monkeypatch):
+    monkeypatch.setenv("BWLA_ENABLE_UNVALIDATED_BATCH", "1")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
@@ -77,18 +33,18 @@ def _check(dtype, gemvs, dots, gi=None, di=None):
 def test_batched_matches_oracle(dtype, acc):
     need_gpu()
     from paper_1409_0669_amd.batch import BatchPlan
-    gemvs, dots = _problems(dtype, 40, 60, 700, 300_000)
+    gemvs, dots = problems(dtype, 40, 60, 700, 300_000)
     plan = BatchPlan(gemvs, dots, acc=acc)
     plan.run()
     torch.cuda.synchronize()
-    _check(dtype, gemvs, dots)
+    check(dtype, gemvs, dots)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_batched_permutation_bitwise_invariant(dtype):
     need_gpu()
     from paper_1409_0669_amd.batch import BatchPlan
-    gemvs, dots = _problems(dtype, 30, 50, 500, 200_000, seed=1)
+    gemvs, dots = problems(dtype, 30, 50, 500, 200_000, seed=1)
     p1 = BatchPlan(gemvs, dots)
     p1.run()
     torch.cuda.synchronize()
@@ -112,7 +68,7 @@ def test_batched_permutation_bitwise_invariant(dtype):
 def test_batched_graph_replay_equals_direct():
     need_gpu()
     from paper_1409_0669_amd.batch import BatchPlan
-    gemvs, dots = _problems("f32", 25, 40, 600, 250_000, seed=2)
+    gemvs, dots = problems("f32", 25, 40, 600, 250_000, seed=2)
     plan = BatchPlan(gemvs, dots)
     plan.run()
     torch.cuda.synchronize()
@@ -140,7 +96,7 @@ def test_batch_of_one_matches_single_call():
     need_gpu()
     from paper_1409_0669_amd import ops
     from paper_1409_0669_amd.batch import BatchPlan
-    gemvs, dots = _problems("f32", 1, 1, 3000, 900_000, seed=3)
+    gemvs, dots = problems("f32", 1, 1, 3000, 900_000, seed=3)
     BatchPlan(gemvs, []).run()
     BatchPlan([], dots).run()
     A, x, y = gemvs[0]
@@ -173,7 +129,7 @@ def test_batched_full_workload_sampled(dtype):
     need_gpu()
     from paper_1409_0669_amd.batch import BatchPlan
     M, N, D = W.batched_sizes(0)
-    gemvs, dots = _from_sizes(dtype, M, N, D, seed=0)
+    gemvs, dots = from_sizes(dtype, M, N, D, seed=0)
     plan = BatchPlan(gemvs, dots, acc="compensated")
     info = plan.info()
     assert info["items"] > 0
@@ -182,7 +138,7 @@ def test_batched_full_workload_sampled(dtype):
     rng = np.random.default_rng(11)
     gi = list(rng.choice(len(gemvs), 12, replace=False)) + [int(np.argmax(M * N))]
     di = list(rng.choice(len(dots), 24, replace=False)) + [int(np.argmax(D))]
-    _check(dtype, gemvs, dots, gi, di)
+    check(dtype, gemvs, dots, gi, di)
     y0 = [host(gemvs[i][2]) for i in gi]
     s = torch.cuda.Stream()
     plan.capture(s)

@@ -1,0 +1,142 @@
+"""Batched launch with one work-group per work item (the plans' default):
+every problem matches the oracle; results are bitwise independent of the batch
+order; graph replays equal the direct launch bitwise; a batch of one matches
+the single-problem call; empty problems; the full uneven workload (sampled)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.batch_util import check, from_sizes, problems
+from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector
+from tests.gpu_util import DT, host, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _grouped(monkeypatch):
+    monkeypatch.delenv("BWLA_ENABLE_UNVALIDATED_BATCH", raising=False)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+def test_grouped_matches_oracle(dtype, acc):
+    need_gpu()
+    from paper_1409_0669_amd.batch import BatchPlan
+    gemvs, dots = problems(dtype, 40, 60, 700, 300_000)
+    plan = BatchPlan(gemvs, dots, acc=acc)
+    plan.run()
+    torch.cuda.synchronize()
+    check(dtype, gemvs, dots)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_grouped_permutation_bitwise_invariant(dtype):
+    need_gpu()
+    from paper_1409_0669_amd.batch import BatchPlan
+    gemvs, dots = problems(dtype, 30, 50, 500, 200_000, seed=1)
+    p1 = BatchPlan(gemvs, dots)
+    p1.run()
+    torch.cuda.synchronize()
+    y1 = [host(g[2]) for g in gemvs]
+    d1 = [host(d[2]) for d in dots]
+    for g in gemvs:
+        g[2].fill_(-7.0)
+    for d in dots:
+        d[2].fill_(-7.0)
+    rng = np.random.default_rng(9)
+    pg, pd = rng.permutation(len(gemvs)), rng.permutation(len(dots))
+    p2 = BatchPlan([gemvs[i] for i in pg], [dots[i] for i in pd], grid=37)
+    p2.run()
+    torch.cuda.synchronize()
+    for i in range(len(gemvs)):
+        assert bitwise_equal(host(gemvs[i][2]), y1[i])
+    for i in range(len(dots)):
+        assert bitwise_equal(host(dots[i][2]), d1[i])
+
+
+def test_grouped_graph_replay_equals_direct():
+    need_gpu()
+    from paper_1409_0669_amd.batch import BatchPlan
+    gemvs, dots = problems("f32", 25, 40, 600, 250_000, seed=2)
+    plan = BatchPlan(gemvs, dots)
+    plan.run()
+    torch.cuda.synchronize()
+    y_ref = [host(g[2]) for g in gemvs]
+    d_ref = [host(d[2]) for d in dots]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture(s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for g in gemvs:
+            g[2].fill_(float(rep) + 0.5)   # eager work between replays
+        for d in dots:
+            d[2].fill_(-1.0)
+        torch.cuda.synchronize()
+        plan.replay()
+        torch.cuda.synchronize()
+        for i in range(len(gemvs)):
+            assert bitwise_equal(host(gemvs[i][2]), y_ref[i]), (rep, i)
+        for i in range(len(dots)):
+            assert bitwise_equal(host(dots[i][2]), d_ref[i]), (rep, i)
+
+
+def test_grouped_batch_of_one_matches_single_call():
+    need_gpu()
+    from paper_1409_0669_amd import ops
+    from paper_1409_0669_amd.batch import BatchPlan
+    gemvs, dots = problems("f32", 1, 1, 3000, 900_000, seed=3)
+    BatchPlan(gemvs, []).run()
+    BatchPlan([], dots).run()
+    A, x, y = gemvs[0]
+    single = ops.gemv(A, x)
+    check_vector(host(y), host(single), np.abs(host(A)) @ np.abs(host(x)), TOL["f32"])
+    p, q, out = dots[0]
+    single = float(ops.dot(p, q).item())
+    check_scalar(float(out.item()), single, 0.0, TOL["f32"])
+
+
+def test_grouped_empty_problems():
+    need_gpu()
+    from paper_1409_0669_amd.batch import BatchPlan
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    out = torch.full((1,), 5.0, device="cuda")
+    A = torch.empty(3, 0, dtype=torch.float32, device="cuda")
+    y = torch.full((3,), 5.0, device="cuda")
+    BatchPlan([(A, e, y)], [(e, e, out)]).run()
+    torch.cuda.synchronize()
+    assert float(out.item()) == 0.0
+    assert torch.all(y == 0)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_grouped_full_workload_sampled(dtype):
+    """512 GEMVs with M, N log-uniform in [32, 4096] and 4096 dots with n
+    log-uniform in [1e3, 1e6], Kahan/Dot2-compensated FP32 accumulation; a
+    sample of problems is checked against the oracle, and a replay of the
+    captured graph must equal the direct launch bitwise."""
+    need_gpu()
+    from paper_1409_0669_amd.batch import BatchPlan
+    M, N, D = W.batched_sizes(0)
+    gemvs, dots = from_sizes(dtype, M, N, D, seed=0)
+    plan = BatchPlan(gemvs, dots, acc="compensated")
+    info = plan.info()
+    assert info["items"] > 0
+    plan.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    gi = list(rng.choice(len(gemvs), 12, replace=False)) + [int(np.argmax(M * N))]
+    di = list(rng.choice(len(dots), 24, replace=False)) + [int(np.argmax(D))]
+    check(dtype, gemvs, dots, gi, di)
+    y0 = [host(gemvs[i][2]) for i in gi]
+    s = torch.cuda.Stream()
+    plan.capture(s)
+    plan.replay()
+    torch.cuda.synchronize()
+    for k, i in enumerate(gi):
+        assert bitwise_equal(host(gemvs[i][2]), y0[k])
