@@ -5,10 +5,14 @@
 * Reductions: many results are correct (the summation order is free), so they
   are compared within a tolerance: 1e-12 for float64 storage, 1e-5 for float32
   and bfloat16 storage (bf16 inputs compared on their quantised values).
-  - dot / nrm2: |got - ref| <= tol * |ref|; when the exact value is 0 by
-    construction, normwise |got - ref| <= tol * sum |x_i y_i|.
-  - GEMV: per output, |got_i - ref_i| <= tol * (|A| |x|)_i (componentwise,
-    condition-scaled), and max |got - ref| <= tol * max |ref|.
+  "Relative" is read as condition-scaled, the same for an inner product and
+  for each output of a GEMV (a one-row GEMV is an inner product):
+  - dot: |got - ref| <= tol * sum |x_i y_i| (for well-conditioned data this
+    is close to tol * |ref|; for ill-conditioned sums no float32-accumulated
+    order can meet tol * |ref|, compensated summation aside);
+  - nrm2: |got - ref| <= tol * |ref| (sum x_i^2 has no cancellation);
+  - GEMV: per output, |got_i - ref_i| <= tol * (|A| |x|)_i, and
+    max |got - ref| <= tol * max |ref|.
 """
 from __future__ import annotations
 
@@ -18,11 +22,15 @@ TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-5}
 
 
 def check_scalar(got: float, ref: float, absum: float, tol: float, what: str = "") -> None:
+    """absum = sum |x_i y_i| for an inner product (condition scale); 0 when the
+    scale is |ref| itself (norms, sums without cancellation)."""
     err = abs(got - ref)
-    if ref != 0.0:
-        assert err <= tol * abs(ref), "%s: rel err %.3e > %.1e (got %r ref %r)" % (what, err / abs(ref), tol, got, ref)
-    else:
-        assert err <= tol * max(absum, 1e-300), "%s: normwise err %.3e (got %r)" % (what, err, got)
+    scale = max(abs(ref), absum)
+    if scale == 0.0:
+        assert got == 0.0, "%s: got %r for an exact zero" % (what, got)
+        return
+    assert err <= tol * scale, "%s: err %.3e > %.1e x scale %.3e (got %r ref %r)" % (
+        what, err, tol, scale, got, ref)
 
 
 def check_vector(got: np.ndarray, ref: np.ndarray, scale: np.ndarray, tol: float, what: str = "") -> None:
