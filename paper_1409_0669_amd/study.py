@@ -43,7 +43,7 @@ def run(sizes=(2_000_000, 1 << 26), dtype=torch.float64, reps=5, log=print):
     cus = L.lib.bwla_device_cus()
     space = tune.vector_space(cus)
     ops.reset_config()
-    out = {"device": torch.cuda.get_device_name(), "cus": cus, "configs": len(space), "sizes": {}}
+    out = {"device": "%s, %s" % (torch.cuda.get_device_name(), torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]), "cus": cus, "configs": len(space), "sizes": {}}
     for n in sizes:
         rates = {}
         for op in OPS:
