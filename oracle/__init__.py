@@ -18,6 +18,9 @@ Operation definitions follow Section 2 of the paper:
 * ``nrm2``   sqrt(<x, x>)
 * ``gemv``   y <- op(A) x, row- or column-major A
 * ``ger``    A <- u v^T                   (gradient of y = A x with respect to A)
+* ``gemv_dot`` y <- op(A) x stored in the storage precision, then <w, y>: the
+  GEMV-then-inner-product pair of a conjugate-gradient iteration, a composite
+  of the two definitions above
 """
 from __future__ import annotations
 
@@ -151,6 +154,19 @@ def gemv(A, x, layout: int = ROW_MAJOR, trans: int = 0, m: int | None = None,
     if out_len:
         _load().o_gemv(layout, int(trans), m, n, _ptr(flat), lda, _ptr(x), _ptr(y))
     return y
+
+
+def gemv_dot(prec, A, x, w, layout: int = ROW_MAJOR, trans: int = 0, m: int | None = None,
+             n: int | None = None, lda: int | None = None):
+    """(y, s): y = op(A) x as stored in ``prec`` ("f64" or "f32": the float64
+    GEMV result, rounded to float32 for f32 storage), and s = <w, y> of that
+    stored y.  Nothing but the two definitions in sequence."""
+    if prec_code(prec) not in (F64, F32):
+        raise ValueError("gemv_dot stores y in float64 or float32")
+    y = gemv(A, x, layout, trans, m, n, lda)
+    if prec_code(prec) == F32:
+        y = y.astype(np.float32).astype(np.float64)  # round to nearest even
+    return y, dot(w, y)
 
 
 def ger(prec, u, v, layout: int = ROW_MAJOR, lda: int | None = None) -> np.ndarray:

@@ -308,6 +308,62 @@ def test_gemv_layout_swap_identity():
     assert np.array_equal(y1, y2)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("trans", [0, 1])
+def test_gemv_dot_f64_exact(layout, trans):
+    """y_i is the correctly rounded row product and s is within the Dot2
+    bound of the exact <w, y> (y as stored), computed with rationals."""
+    m, n = 9, 13
+    rng = np.random.default_rng(31 + trans)
+    A = rng.uniform(-1, 1, (m, n))
+    x = rng.uniform(-1, 1, m if trans else n)
+    w = rng.uniform(-1, 1, n if trans else m)
+    flat, lda = _flat(A, layout, pad=2)
+    y, s = oracle.gemv_dot("f64", flat, x, w, layout=layout, trans=trans, m=m, n=n, lda=lda)
+    B = A.T if trans else A
+    for i in range(B.shape[0]):
+        assert y[i] == float(exact_dot(B[i], x)), i
+    ex = exact_dot(w, y)
+    absum = sum(abs(Fraction(float(a)) * Fraction(float(b))) for a, b in zip(w, y))
+    assert abs(Fraction(s) - ex) <= Fraction(dot2_bound(len(w), ex, absum))
+
+
+def test_gemv_dot_f32_rounds_y_before_the_inner_product():
+    """With f32 storage the inner product takes the stored (rounded) y:
+    rows (1, 2^-30) and (3, 2^-28) against x = (1, 1) give y = (1, 3) in
+    float32, so <w, y> = 1 + 3 = 4, not 4 + 5 * 2^-30."""
+    A = np.array([[1.0, 2.0 ** -30], [3.0, 2.0 ** -28]])
+    y, s = oracle.gemv_dot("f32", A, np.ones(2), np.ones(2))
+    assert y.tolist() == [1.0, 3.0] and s == 4.0
+    y, s = oracle.gemv_dot("f64", A, np.ones(2), np.ones(2))
+    assert s == 4.0 + 5 * 2.0 ** -30
+    # a value halfway between two floats rounds to the even one
+    y, _ = oracle.gemv_dot("f32", np.array([[1.0, 2.0 ** -24]]), np.ones(2), np.ones(1))
+    assert y[0] == 1.0
+    y, _ = oracle.gemv_dot("f32", np.array([[1.0 + 2.0 ** -23, 2.0 ** -24]]), np.ones(2), np.ones(1))
+    assert y[0] == 1.0 + 2.0 ** -22
+
+
+def test_gemv_dot_small_integers_and_quadratic_form():
+    """Small integers are exact throughout: y = A x and s = w^T A x; with
+    A = I and w = x the result is the squared norm."""
+    rng = np.random.default_rng(12)
+    A = rng.integers(-6, 7, (40, 30)).astype(np.float64)
+    x = rng.integers(-6, 7, 30).astype(np.float64)
+    w = rng.integers(-6, 7, 40).astype(np.float64)
+    for prec in ("f64", "f32"):
+        y, s = oracle.gemv_dot(prec, A, x, w)
+        assert y.tolist() == (A @ x).tolist()
+        assert s == float(sum(int(a) * int(b) for a, b in zip(w, A @ x)))
+    y, s = oracle.gemv_dot("f64", A.T, w, x, layout=oracle.ROW_MAJOR, trans=0)
+    y2, s2 = oracle.gemv_dot("f64", A, w, x, trans=1)
+    assert y.tolist() == y2.tolist() and s == s2
+    _, s = oracle.gemv_dot("f64", np.eye(30), x, x)
+    assert s == float(x @ x)
+    with pytest.raises(ValueError):
+        oracle.gemv_dot("bf16", A, x, w)
+
+
 def test_gemv_empty():
     assert oracle.gemv(np.zeros((0, 5)), np.ones(5)).size == 0
     assert np.array_equal(oracle.gemv(np.zeros((4, 0)), np.ones(0)), np.zeros(4))
