@@ -190,6 +190,8 @@ def extra_rows(torch, W, ops, reps):
     pv = W.device_draw(m, "f64", 0, 931, dist="normal")
     q = torch.empty(m, dtype=torch.float64, device="cuda")
     rate("composite gemv 8192^2 + dot f64", (m * m + 3 * m) * 8, lambda: composite.gemv_dot(A, pv, q=q))
+    rate("composite gemv 8192^2 + dot f64 fused epilogue (same work)", (m * m + 3 * m) * 8,
+         lambda: composite.gemv_dot_fused(A, pv, q=q))
     del A
     return out
 

@@ -146,6 +146,33 @@ bwla_status bwla_gemv(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans,
                       int64_t n, const void *A, int64_t lda, const void *x, bwla_dtype out_t,
                       void *y, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- matrix-vector product with an inner-product epilogue -----------------
+ * y <- op(A) x exactly as bwla_gemv with out_t = t, and in the same launch
+ * sequence dot <- <w, y> = sum_i w_i y_i over the out_len entries of y, taken
+ * with y as stored.  This is the GEMV-then-inner-product pair of one
+ * conjugate-gradient iteration (q = A p followed by <p, q>), one of the
+ * composite operations that the paper's abstract expects to inherit the
+ * tuned kernels' performance; it is fused so that y and w are not read back
+ * after the GEMV: each work-group that
+ * stores outputs also reduces w_i y_i over them to a float64 partial, and
+ * the partials are summed in a fixed order as in bwla_dot.
+ * t is BWLA_F64 or BWLA_F32 (BWLA_ERR_UNSUPPORTED for BWLA_BF16, whose GEMV
+ * output is never bf16).  w has out_len entries of type t (out_len = m for
+ * trans == 0, n for trans == 1) and may alias x; dot is ONE device element of
+ * dot_t (BWLA_F64 for f64; BWLA_F32 or BWLA_F64 for f32).  y must not
+ * overlap A, x or w; dot must not overlap A, x, y or w.  out_len == 0 writes
+ * dot = 0 only; a zero-length reduction writes y = 0 and dot = 0.
+ * Workspace: at least bwla_gemv_dot_workspace_size() bytes. */
+bwla_status bwla_gemv_dot(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m,
+                          int64_t n, const void *A, int64_t lda, const void *x, void *y,
+                          const void *w, bwla_dtype dot_t, void *dot, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* Bytes of workspace bwla_gemv_dot needs for these arguments under the
+ * current configuration table (at least what bwla_gemv needs). */
+bwla_status bwla_gemv_dot_workspace_size(bwla_dtype t, bwla_layout layout, int trans, int64_t m,
+                                         int64_t n, size_t *bytes);
+
 /* ---- rank-1 overwrite: A <- u v^T ------------------------------------------
  * The gradient of y = A x with respect to A for an incoming gradient u = ybar
  * and v = x.  A is m x n in the given layout and leading dimension; every

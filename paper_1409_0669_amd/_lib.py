@@ -51,6 +51,9 @@ SIGNATURES = {
     "bwla_dot": (c_int, [c_int, c_int, i64, vp, vp, c_int, vp, vp, sz, vp]),
     "bwla_nrm2": (c_int, [c_int, c_int, i64, vp, c_int, vp, vp, sz, vp]),
     "bwla_gemv": (c_int, [c_int, c_int, c_int, c_int, i64, i64, vp, i64, vp, c_int, vp, vp, sz, vp]),
+    "bwla_gemv_dot": (c_int, [c_int, c_int, c_int, c_int, i64, i64, vp, i64, vp, vp, vp, c_int, vp, vp,
+                              sz, vp]),
+    "bwla_gemv_dot_workspace_size": (c_int, [c_int, c_int, c_int, i64, i64, ctypes.POINTER(sz)]),
     "bwla_ger": (c_int, [c_int, c_int, i64, i64, vp, vp, vp, i64, vp]),
     "bwla_cg_update": (c_int, [c_int, c_int, i64, dbl, vp, vp, vp, vp, vp, c_int, vp, vp, sz, vp]),
     "bwla_workspace_size": (c_int, [c_int, c_int, c_int, c_int, c_int, i64, i64, ctypes.POINTER(sz)]),

@@ -8,7 +8,8 @@ are fast too (abstract; Section 3.4).
 * ``cg_step_fused``: the same step in one pass (6 n elements, one launch plus
   the reduction's second stage); elementwise results are bitwise those of
   ``cg_step``.
-* ``gemv_dot``: q = A p followed by <p, q>.
+* ``gemv_dot``: q = A p followed by <p, q>; ``gemv_dot_fused`` the same with
+  the inner product in the GEMV's epilogue.
 """
 from __future__ import annotations
 
@@ -31,7 +32,13 @@ def cg_step_fused(a: float, x, p, r, q, acc="plain", alpha_dev=None):
 
 
 def gemv_dot(A, p, acc="plain", q=None):
+    """q = A p and <p, q> as two library calls."""
     q = ops.gemv(A, p, acc=acc, out=q)
     if q.dtype != p.dtype:
         raise ops.BwlaError(2, "gemv_dot needs the GEMV output in the storage type (float64 or float32)")
     return q, ops.dot(p, q, acc=acc)
+
+
+def gemv_dot_fused(A, p, acc="plain", q=None):
+    """q = A p and <p, q> with the inner product in the GEMV's epilogue."""
+    return ops.gemv_dot(A, p, acc=acc, out=q)

@@ -491,10 +491,31 @@ static GemvPlan gemv_plan(int layout, int trans, int64_t m, int64_t n)
     return g;
 }
 
-bwla_status bwla_gemv(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m, int64_t n,
-                      const void *A, int64_t lda, const void *x, bwla_dtype out_t, void *y, void *ws,
-                      size_t ws_bytes, void *stream)
+// Workspace of a GEMV, and of a GEMV with the dot epilogue: the split
+// partials, then (with the epilogue) one float64 pair per work-group that
+// stores y.
+static size_t gemv_ws(const GemvPlan &g, const Cfg &c, bool with_dot, size_t *dparts_offset)
 {
+    const size_t base = g.rows ? ws_rows(c, g.L) : ws_cols(c, g.K);
+    if (dparts_offset)
+        *dparts_offset = base;
+    if (!with_dot)
+        return base;
+    return base + (size_t)gemv_dot_parts(g.rows, g.L, g.K, c) * sizeof(DD);
+}
+
+static Cfg gemv_cfg(bwla_dtype t, const GemvPlan &g, const void *A, int64_t lda, const void *x)
+{
+    return g.rows ? resolve_rows(t, g.L, g.K, A, lda, x) : resolve_cols(t, g.L, g.K, A, lda, x);
+}
+
+// Shared body of bwla_gemv and bwla_gemv_dot (w == NULL: no epilogue).
+static bwla_status gemv_common(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m,
+                               int64_t n, const void *A, int64_t lda, const void *x, bwla_dtype out_t,
+                               void *y, const void *w, bwla_dtype dot_t, void *dot, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    const bool fused = dot != nullptr;
     if (!valid_dtype(t))
         return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
     if (acc != BWLA_ACC_PLAIN && acc != BWLA_ACC_COMPENSATED)
@@ -508,45 +529,103 @@ bwla_status bwla_gemv(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans,
     bwla_status st = out_type_ok(t, out_t);
     if (st)
         return st;
+    if (fused) {
+        if (t == BWLA_BF16)
+            return fail(BWLA_ERR_UNSUPPORTED, "gemv_dot needs y in the storage type; bf16 has no bf16 GEMV output");
+        if ((st = out_type_ok(t, dot_t)))
+            return st;
+    }
     GemvPlan g = gemv_plan(layout, trans, m, n);
     if (lda < std::max<int64_t>(1, g.K))
         return fail(BWLA_ERR_INVALID_ARG, "lda %lld < %lld", (long long)lda, (long long)std::max<int64_t>(1, g.K));
+    const size_t es = dsize(t), os = out_t == BWLA_F64 ? 8 : 4;
+    hipStream_t s = (hipStream_t)stream;
+    if (fused) {
+        Span sd = span(dot, dot_t == BWLA_F64 ? 8 : 4);
+        if (g.out_len > 0 && (!y || !w))
+            return fail(BWLA_ERR_INVALID_ARG, "y or w is NULL");
+        if (g.out_len > 0 && (overlaps(sd, span(y, g.out_len * os)) || overlaps(sd, span(w, g.out_len * es))))
+            return fail(BWLA_ERR_INVALID_ARG, "dot overlaps y or w");
+        if (g.in_len > 0 && g.out_len > 0 &&
+            (overlaps(sd, span(A, matrix_bytes(g.L, g.K, lda, es))) || overlaps(sd, span(x, g.in_len * es))))
+            return fail(BWLA_ERR_INVALID_ARG, "dot overlaps A or x");
+        if (g.out_len > 0 && overlaps(span(y, g.out_len * os), span(w, g.out_len * es)))
+            return fail(BWLA_ERR_INVALID_ARG, "y overlaps w");
+    }
     if (g.out_len == 0)
-        return BWLA_OK;
+        return fused ? hip_check(launch_fill_zero(dot, 1, dot_t == BWLA_F64, s), "fill launch") : BWLA_OK;
     if (!y)
         return fail(BWLA_ERR_INVALID_ARG, "y is NULL");
-    const size_t es = dsize(t), os = out_t == BWLA_F64 ? 8 : 4;
     if (g.in_len > 0 && (!A || !x))
         return fail(BWLA_ERR_INVALID_ARG, "NULL A or x with a nonzero reduction length");
     Span sy = span(y, g.out_len * os);
     if (g.in_len > 0 && (overlaps(sy, span(A, matrix_bytes(g.L, g.K, lda, es))) ||
                          overlaps(sy, span(x, g.in_len * es))))
         return fail(BWLA_ERR_INVALID_ARG, "y overlaps A or x");
-    if (g.in_len == 0)
-        return hip_check(launch_fill_zero(y, g.out_len, out_t == BWLA_F64, (hipStream_t)stream), "fill launch");
-    const bool comp = acc == BWLA_ACC_COMPENSATED;
-    const int of64 = out_t == BWLA_F64;
-    hipStream_t s = (hipStream_t)stream;
-    if (g.rows) {
-        Cfg c = resolve_rows(t, g.L, g.K, A, lda, x);
-        const size_t need = ws_rows(c, g.L);
-        if (need && (!ws || ws_bytes < need))
-            return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-        hipError_t e = by_type(t, [&](auto *tag) {
-            using T = std::remove_pointer_t<decltype(tag)>;
-            return launch_gemv_rows<T>(g.L, g.K, comp, A, lda, x, of64, y, ws, c, s);
-        });
-        return hip_check(e, "gemv (rows) launch");
+    if (g.in_len == 0) {
+        bwla_status r = hip_check(launch_fill_zero(y, g.out_len, out_t == BWLA_F64, s), "fill launch");
+        if (r || !fused)
+            return r;
+        return hip_check(launch_fill_zero(dot, 1, dot_t == BWLA_F64, s), "fill launch");
     }
-    Cfg c = resolve_cols(t, g.L, g.K, A, lda, x);
-    const size_t need = ws_cols(c, g.K);
+    const bool comp = acc == BWLA_ACC_COMPENSATED;
+    const int of64 = out_t == BWLA_F64, df64 = dot_t == BWLA_F64;
+    Cfg c = gemv_cfg(t, g, A, lda, x);
+    size_t off = 0;
+    const size_t need = gemv_ws(g, c, fused, &off);
     if (need && (!ws || ws_bytes < need))
         return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    const void *wv = fused ? w : nullptr;
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
-        return launch_gemv_cols<T>(g.L, g.K, comp, A, lda, x, of64, y, ws, c, s);
+        if (g.rows)
+            return launch_gemv_rows<T>(g.L, g.K, comp, A, lda, x, of64, y, ws, c, s, wv, off, df64, dot);
+        return launch_gemv_cols<T>(g.L, g.K, comp, A, lda, x, of64, y, ws, c, s, wv, off, df64, dot);
     });
-    return hip_check(e, "gemv (cols) launch");
+    return hip_check(e, g.rows ? "gemv (rows) launch" : "gemv (cols) launch");
+}
+
+bwla_status bwla_gemv(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m, int64_t n,
+                      const void *A, int64_t lda, const void *x, bwla_dtype out_t, void *y, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    return gemv_common(t, acc, layout, trans, m, n, A, lda, x, out_t, y, nullptr, out_t, nullptr, ws,
+                       ws_bytes, stream);
+}
+
+bwla_status bwla_gemv_dot(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m, int64_t n,
+                          const void *A, int64_t lda, const void *x, void *y, const void *w,
+                          bwla_dtype dot_t, void *dot, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!dot)
+        return fail(BWLA_ERR_INVALID_ARG, "dot is NULL");
+    return gemv_common(t, acc, layout, trans, m, n, A, lda, x, t, y, w, dot_t, dot, ws, ws_bytes, stream);
+}
+
+bwla_status bwla_gemv_dot_workspace_size(bwla_dtype t, bwla_layout layout, int trans, int64_t m, int64_t n,
+                                         size_t *bytes)
+{
+    if (!bytes)
+        return fail(BWLA_ERR_INVALID_ARG, "bytes is NULL");
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
+        return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
+    if (trans != 0 && trans != 1)
+        return fail(BWLA_ERR_INVALID_ARG, "trans %d", trans);
+    if (m < 0 || n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "negative size");
+    *bytes = 0;
+    GemvPlan g = gemv_plan(layout, trans, m, n);
+    if (g.out_len == 0 || g.in_len == 0)
+        return BWLA_OK; // only fills run
+    size_t best = 0; // largest over the pack widths the call could end up with
+    for (int v = 1; v <= 16; v <<= 1) {
+        const void *fake = (const void *)(uintptr_t)(v * dsize(t));
+        best = std::max(best, gemv_ws(g, gemv_cfg(t, g, fake, v, fake), true, nullptr));
+    }
+    *bytes = best;
+    return BWLA_OK;
 }
 
 bwla_status bwla_ger(bwla_dtype t, bwla_layout layout, int64_t m, int64_t n, const void *u, const void *v,

@@ -24,15 +24,31 @@
 //   wave-uniform broadcast.  Per-wave partial sums are combined through LDS in
 //   wave order; with split > 1 the slices' partials are combined in slice
 //   order by a second kernel.
+//
+// Dot epilogue (w != NULL): the caller also wants s = <w, y> over the
+// outputs, with y as stored (the storage type equals the compute type
+// here).  Whichever kernel stores an output also forms w_o * y_o and reduces
+// those products over its outputs to one float64 pair per work-group:
+// the rows or cols kernel when split == 1, the line combine otherwise.  The
+// scalar second stage then sums the pairs in work-group order.  This saves
+// re-reading y and w and one launch of the separate inner product.
 #include "device.hpp"
 #include "kernels.hpp"
 
 namespace bwla {
 
+// One product of the dot epilogue, left as a float64 pair.
+template <typename C, bool COMP> __device__ __forceinline__ DD epilogue_term(C w, C y)
+{
+    Acc<C, COMP> a;
+    a.template add_prod<false>(w, y);
+    return a.to_dd();
+}
+
 template <typename T, int V, int R, bool COMP>
 __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const T *A, int64_t ld,
                                                     const T *v, DD *partials, void *out, int out_f64,
-                                                    int split)
+                                                    int split, const T *w, DD *dparts)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -82,10 +98,11 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
             lds[wave * R + r] = d;
     }
     __syncthreads();
+    DD t = {0.0, 0.0};
     if (threadIdx.x < R) {
-        DD t = lds[threadIdx.x];
-        for (int w = 1; w < nw; ++w)
-            t = combine<COMP>(t, lds[w * R + threadIdx.x]);
+        t = lds[threadIdx.x];
+        for (int wv = 1; wv < nw; ++wv)
+            t = combine<COMP>(t, lds[wv * R + threadIdx.x]);
         if (split == 1) {
             if (threadIdx.x < nr)
                 store_out(out, l0 + threadIdx.x, out_f64, t.hi + t.lo);
@@ -93,12 +110,20 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
             partials[(group * split + s) * R + threadIdx.x] = t;
         }
     }
+    if (w != nullptr && split == 1 && wave == 0) { // the whole first wave
+        DD d = {0.0, 0.0};
+        if (threadIdx.x < nr)
+            d = epilogue_term<C, COMP>(widen(w[l0 + threadIdx.x]), (C)(t.hi + t.lo));
+        d = wave_sum<COMP>(d);
+        if (lane == 0)
+            dparts[group] = d;
+    }
 }
 
 template <typename T, int V, int U, bool COMP>
 __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const T *A, int64_t ld,
                                                     const T *v, DD *partials, void *out, int out_f64,
-                                                    int split)
+                                                    int split, const T *w, DD *dparts)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -190,88 +215,132 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
                 partials[(tile * split + s) * TK + lane * V + e] = d[e];
             }
         }
+        if (w != nullptr && split == 1) {
+            DD t = {0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (k0 + e < K)
+                    t = combine<COMP>(t, epilogue_term<C, COMP>(widen(w[k0 + e]), (C)(d[e].hi + d[e].lo)));
+            t = wave_sum<COMP>(t);
+            if (lane == 0)
+                dparts[tile] = t;
+        }
     }
 }
 
 #if BWLA_T_IS_F64 // type-independent kernels live in the f64 object only
 // Second stage of a split GEMV: one thread per output sums its slices' float64
 // partials in slice order.  Consecutive outputs read consecutive partials.
+// With w (same element type as out), the work-group also reduces w_o * y_o
+// over its outputs into dparts[blockIdx.x].
 template <bool COMP>
 __global__ __launch_bounds__(256) void k_combine_lines(const DD *partials, int64_t outputs, int64_t G,
-                                                       int64_t split, void *out, int out_f64)
+                                                       int64_t split, void *out, int out_f64,
+                                                       const void *w, DD *dparts)
 {
+    __shared__ DD lds[16];
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= outputs)
+    const bool live = o < outputs;
+    double y = 0.0;
+    if (live) {
+        const int64_t g = o / G, r = o - g * G;
+        const DD *p = partials + g * split * G + r;
+        DD t = p[0];
+        for (int64_t q = 1; q < split; ++q)
+            t = combine<COMP>(t, p[q * G]);
+        y = t.hi + t.lo;
+        store_out(out, o, out_f64, y);
+    }
+    if (w == nullptr)
         return;
-    const int64_t g = o / G, r = o - g * G;
-    const DD *p = partials + g * split * G + r;
-    DD t = p[0];
-    for (int64_t q = 1; q < split; ++q)
-        t = combine<COMP>(t, p[q * G]);
-    store_out(out, o, out_f64, t.hi + t.lo);
+    DD d = {0.0, 0.0};
+    if (live) {
+        if (out_f64)
+            d = epilogue_term<double, COMP>(reinterpret_cast<const double *>(w)[o], y);
+        else
+            d = epilogue_term<float, COMP>(reinterpret_cast<const float *>(w)[o], (float)y);
+    }
+    d = block_sum<COMP>(d, lds);
+    if (threadIdx.x == 0)
+        dparts[blockIdx.x] = d;
 }
 
 hipError_t launch_combine_lines(const void *partials, int64_t outputs, int64_t G, int64_t split,
-                                bool comp, int out_f64, void *out, hipStream_t s)
+                                bool comp, int out_f64, void *out, const void *w, void *dparts,
+                                hipStream_t s)
 {
     const int64_t blocks = (outputs + 255) / 256;
     return with_bool(comp, [&](auto CP) {
         hipLaunchKernelGGL((k_combine_lines<CP.value>), dim3((unsigned)blocks), dim3(256), 0, s,
-                           (const DD *)partials, outputs, G, split, out, out_f64);
+                           (const DD *)partials, outputs, G, split, out, out_f64, w, (DD *)dparts);
         return hipGetLastError();
     });
 }
 #endif
 
+
+// Workspace: [split partials of the GEMV][dot-epilogue pairs].  With w the
+// epilogue pairs are then summed into *dot by the scalar combine.
 template <typename T>
 hipError_t launch_gemv_rows(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
                             const void *v, int out_f64, void *out, void *ws, const Cfg &c,
-                            hipStream_t s)
+                            hipStream_t s, const void *w, size_t dparts_offset, int dot_f64,
+                            void *dot)
 {
     DD *partials = (DD *)ws;
+    DD *dparts = w ? (DD *)((char *)ws + dparts_offset) : nullptr;
     hipError_t e = with_vec(c.vec, [&](auto V) {
         return with_rows(c.rows, [&](auto R) {
             return with_bool(comp, [&](auto CP) {
                 const int64_t groups = (L + R.value - 1) / R.value;
                 hipLaunchKernelGGL((k_gemv_rows<T, V.value, R.value, CP.value>),
                                    dim3((unsigned)(groups * c.split)), dim3(c.block), 0, s, L, K,
-                                   (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split);
+                                   (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split,
+                                   (const T *)w, dparts);
                 return hipGetLastError();
             });
         });
     });
-    if (e != hipSuccess || c.split == 1)
+    if (e == hipSuccess && c.split > 1)
+        e = launch_combine_lines(partials, L, c.rows, c.split, comp, out_f64, out, w, dparts, s);
+    if (e != hipSuccess || !w)
         return e;
-    return launch_combine_lines(partials, L, c.rows, c.split, comp, out_f64, out, s);
+    return launch_combine_scalar(dparts, gemv_dot_parts(true, L, K, c), comp, false, dot_f64, dot, s);
 }
 
 template <typename T>
 hipError_t launch_gemv_cols(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
                             const void *v, int out_f64, void *out, void *ws, const Cfg &c,
-                            hipStream_t s)
+                            hipStream_t s, const void *w, size_t dparts_offset, int dot_f64,
+                            void *dot)
 {
     DD *partials = (DD *)ws;
+    DD *dparts = w ? (DD *)((char *)ws + dparts_offset) : nullptr;
     hipError_t e = with_vec(c.vec, [&](auto V) {
         return with_unroll(c.unroll, [&](auto U) {
             return with_bool(comp, [&](auto CP) {
                 const int64_t tiles = (K + 64 * V.value - 1) / (64 * V.value);
                 hipLaunchKernelGGL((k_gemv_cols<T, V.value, U.value, CP.value>),
                                    dim3((unsigned)(tiles * c.split)), dim3(c.block), 0, s, L, K,
-                                   (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split);
+                                   (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split,
+                                   (const T *)w, dparts);
                 return hipGetLastError();
             });
         });
     });
-    if (e != hipSuccess || c.split == 1)
+    if (e == hipSuccess && c.split > 1)
+        e = launch_combine_lines(partials, K, 64 * (int64_t)c.vec, c.split, comp, out_f64, out, w,
+                                 dparts, s);
+    if (e != hipSuccess || !w)
         return e;
-    return launch_combine_lines(partials, K, 64 * (int64_t)c.vec, c.split, comp, out_f64, out, s);
+    return launch_combine_scalar(dparts, gemv_dot_parts(false, L, K, c), comp, false, dot_f64, dot, s);
 }
 
 template hipError_t launch_gemv_rows<BWLA_T>(int64_t, int64_t, bool, const void *, int64_t,
                                              const void *, int, void *, void *, const Cfg &,
-                                             hipStream_t);
+                                             hipStream_t, const void *, size_t, int, void *);
 template hipError_t launch_gemv_cols<BWLA_T>(int64_t, int64_t, bool, const void *, int64_t,
                                              const void *, int, void *, void *, const Cfg &,
-                                             hipStream_t);
+                                             hipStream_t, const void *, size_t, int, void *);
 
 } // namespace bwla

@@ -76,14 +76,30 @@ hipError_t launch_dot(int64_t n, bool comp, bool square, const void *x, const vo
 // A line is a contiguous run of K elements; lines are ld apart.
 //   rows kernel:  out[l] = sum_k A[l*ld + k] * v[k]     (l < L)
 //   cols kernel:  out[k] = sum_l A[l*ld + k] * v[l]     (k < K)
+// ws holds the split partials from offset 0.  With w != NULL (same element
+// type as out, one entry per output) the launch also writes
+// *dot = sum_o w[o] * out[o], using gemv_dot_parts() float64 pairs at byte
+// offset dparts_offset of ws.
 template <typename T>
 hipError_t launch_gemv_rows(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
                             const void *v, int out_f64, void *out, void *ws, const Cfg &c,
-                            hipStream_t s);
+                            hipStream_t s, const void *w = nullptr, size_t dparts_offset = 0,
+                            int dot_f64 = 1, void *dot = nullptr);
 template <typename T>
 hipError_t launch_gemv_cols(int64_t L, int64_t K, bool comp, const void *A, int64_t ld,
                             const void *v, int out_f64, void *out, void *ws, const Cfg &c,
-                            hipStream_t s);
+                            hipStream_t s, const void *w = nullptr, size_t dparts_offset = 0,
+                            int dot_f64 = 1, void *dot = nullptr);
+// Number of float64 pairs the dot epilogue writes: one per work-group of the
+// kernel that stores y (the rows or cols kernel, or the line combine when
+// split > 1).
+inline int64_t gemv_dot_parts(bool rows, int64_t L, int64_t K, const Cfg &c)
+{
+    const int64_t outputs = rows ? L : K;
+    if (c.split > 1)
+        return (outputs + 255) / 256;
+    return rows ? (L + c.rows - 1) / c.rows : (K + 64 * (int64_t)c.vec - 1) / (64 * (int64_t)c.vec);
+}
 // --- rank-1 overwrite: A[l*ld + k] = a[l] * b[k] ---------------------------
 template <typename T>
 hipError_t launch_ger(int64_t L, int64_t K, const void *a, const void *b, void *A, int64_t ld,
@@ -97,9 +113,12 @@ hipError_t launch_fill_zero(void *out, int64_t count, int out_f64, hipStream_t s
 hipError_t launch_combine_scalar(const void *partials, int64_t count, bool comp, bool do_sqrt,
                                  int out_f64, void *out, hipStream_t s);
 // out[o] = sum over q < split of partials[((o / G) * split + q) * G + o % G],
-// for o < outputs: the slices of a split GEMV combined in slice order.
+// for o < outputs: the slices of a split GEMV combined in slice order.  With
+// w != NULL, work-group b also writes dparts[b] = sum of w[o] * out[o] over
+// its 256 outputs.
 hipError_t launch_combine_lines(const void *partials, int64_t outputs, int64_t G, int64_t split,
-                                bool comp, int out_f64, void *out, hipStream_t s);
+                                bool comp, int out_f64, void *out, const void *w, void *dparts,
+                                hipStream_t s);
 
 // --- batched persistent kernel ----------------------------------------------
 struct BatchItem {

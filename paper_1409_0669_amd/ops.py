@@ -215,6 +215,39 @@ def gemv(A: torch.Tensor, x: torch.Tensor, trans: bool = False, acc="plain",
     return y
 
 
+def gemv_dot(A: torch.Tensor, x: torch.Tensor, w: torch.Tensor | None = None, trans: bool = False,
+             acc="plain", dot_dtype: torch.dtype | None = None, out: torch.Tensor | None = None,
+             dot_out: torch.Tensor | None = None):
+    """(y, s): y = op(A) x in A's dtype (float64 or float32) and s = <w, y> in
+    one fused launch sequence.  ``w`` defaults to ``x`` (the q = A p, <p, q>
+    pair of a conjugate-gradient iteration; op(A) must then be square)."""
+    if not A.is_cuda:
+        raise BwlaError(L.ERR_INVALID_ARG, "A must be a GPU tensor")
+    if A.dtype not in (torch.float64, torch.float32):
+        raise BwlaError(L.ERR_UNSUPPORTED, "gemv_dot stores y in A's dtype: float64 or float32")
+    layout, lda = matrix_layout(A)
+    w = x if w is None else w
+    _vec(x, "x")
+    _vec(w, "w")
+    _same(A.dtype, A.device, x, w)
+    m, n = A.shape
+    out_len, in_len = (n, m) if trans else (m, n)
+    if x.numel() != in_len or w.numel() != out_len:
+        raise BwlaError(L.ERR_INVALID_ARG, "x needs %d entries and w %d" % (in_len, out_len))
+    y = torch.empty(out_len, dtype=A.dtype, device=A.device) if out is None else out
+    _vec(y, "out")
+    if y.numel() != out_len or y.dtype != A.dtype:
+        raise BwlaError(L.ERR_INVALID_ARG, "out must have %d %s entries" % (out_len, A.dtype))
+    s, sc = _scalar_out(A.dtype, dot_dtype, A.device, dot_out)
+    nbytes = ctypes.c_size_t()
+    check(lib.bwla_gemv_dot_workspace_size(dtype_code(A.dtype), layout, int(trans), m, n, ctypes.byref(nbytes)))
+    ws, wsn = _ws_ptr(workspace(nbytes.value, A.device))
+    check(lib.bwla_gemv_dot(dtype_code(A.dtype), _ACC[acc], layout, int(trans), m, n, A.data_ptr(), lda,
+                            x.data_ptr(), y.data_ptr(), w.data_ptr(), sc, s.data_ptr(), ws, wsn,
+                            _stream(A.device)))
+    return y, s
+
+
 def ger(u: torch.Tensor, v: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
     """A <- u v^T (overwrite), every entry rounded once to A's dtype.  ``out``
     is the m x n matrix to overwrite; its layout is read from its strides."""

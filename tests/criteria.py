@@ -13,6 +13,9 @@
   - nrm2: |got - ref| <= tol * |ref| (sum x_i^2 has no cancellation);
   - GEMV: per output, |got_i - ref_i| <= tol * (|A| |x|)_i, and
     max |got - ref| <= tol * max |ref|.
+  - GEMV followed by <w, y> (fused or not): |got - ref| <= 2 tol *
+    sum_i |w_i| (|A| |x|)_i, the GEMV bound carried through w plus the
+    inner product's own bound (sum |w_i y_i| is no larger).
 """
 from __future__ import annotations
 

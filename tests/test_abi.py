@@ -188,3 +188,48 @@ def test_empty_gemv_needs_no_workspace(L):
     assert b.value == 0
     assert L.lib.bwla_workspace_size(L.OP_GEMV_ROWS, 0, 0, 0, 0, 4, 0, ctypes.byref(b)) == L.OK
     assert b.value == 0
+
+
+def test_gemv_dot_validation(L):
+    """bwla_gemv_dot: argument errors are caught before anything is enqueued."""
+    lib = L.lib
+    A, x, y, w, d = FAKE, FAKE + (1 << 30), FAKE + (2 << 30), FAKE + (3 << 30), FAKE + (4 << 30)
+    ws = FAKE + (5 << 30)
+    big = 1 << 24
+    # bf16 storage has no bf16 GEMV output
+    assert lib.bwla_gemv_dot(2, 0, 0, 0, 10, 20, A, 20, x, y, w, 1, d, ws, big, None) == L.ERR_UNSUPPORTED
+    # dot type: f32 inner product of f64 data is not offered
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 20, x, y, w, 1, d, ws, big, None) == L.ERR_UNSUPPORTED
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 20, x, y, w, 0, None, ws, big, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 20, x, y, None, 0, d, ws, big, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 19, x, y, w, 0, d, ws, big, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot(0, 0, 0, 2, 10, 20, A, 20, x, y, w, 0, d, ws, big, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot(0, 5, 0, 0, 10, 20, A, 20, x, y, w, 0, d, ws, big, None) == L.ERR_UNSUPPORTED
+    # overlaps: y with w, dot with y, dot with w, dot inside A, y inside x
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 20, x, y, y + 8, 0, d, ws, big, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 20, x, y, w, 0, y + 16, ws, big, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 20, x, y, w, 0, w, ws, big, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 20, x, y, w, 0, A + 80, ws, big, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 10, 20, A, 20, x, x + 8, w, 0, d, ws, big, None) == L.ERR_INVALID_ARG
+    # w may alias x (both read only): only the workspace is missing here
+    assert lib.bwla_gemv_dot(0, 0, 0, 0, 20, 20, A, 20, x, y, x, 0, d, None, 0, None) == L.ERR_WORKSPACE
+
+
+def test_gemv_dot_workspace_size(L):
+    lib = L.lib
+    b, g = ctypes.c_size_t(), ctypes.c_size_t()
+    for t in (0, 1):
+        for layout in (0, 1):
+            for trans in (0, 1):
+                for (m, n) in [(1, 1), (37, 3000), (3000, 37), (8192, 8192), (16384, 16384)]:
+                    assert lib.bwla_gemv_dot_workspace_size(t, layout, trans, m, n, ctypes.byref(b)) == L.OK
+                    assert lib.bwla_workspace_size(L.OP_GEMV_ROWS, t, 0, layout, trans, m, n,
+                                                   ctypes.byref(g)) == L.OK
+                    # the epilogue adds at least one float64 pair to the GEMV's own partials
+                    assert b.value >= g.value + 16, (t, layout, trans, m, n)
+                    assert b.value % 16 == 0
+    assert lib.bwla_gemv_dot_workspace_size(0, 0, 0, 0, 5, ctypes.byref(b)) == L.OK and b.value == 0
+    assert lib.bwla_gemv_dot_workspace_size(0, 0, 0, 5, 0, ctypes.byref(b)) == L.OK and b.value == 0
+    assert lib.bwla_gemv_dot_workspace_size(0, 0, 0, -1, 5, ctypes.byref(b)) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot_workspace_size(0, 3, 0, 1, 5, ctypes.byref(b)) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_dot_workspace_size(0, 0, 0, 1, 5, None) == L.ERR_INVALID_ARG
