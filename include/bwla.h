@@ -202,7 +202,7 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha,
 bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_layout layout,
                                 int trans, int64_t m, int64_t n, size_t *bytes);
 
-/* ---- batched uneven problems in one persistent launch -------------------
+/* ---- batched uneven problems in one launch -------------------------------
  * A plan holds many row-major GEMVs (y = A x, out_t output) and many dots
  * (out = <x, y>, out_t output) of one storage type.  Work is flattened into
  * items (row tiles of a GEMV, chunks of a dot) ordered largest first and run
@@ -217,6 +217,8 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
  * capture: records the same kernels into a HIP graph owned by the plan.
  * replay: launches the captured graph.
  * Descriptor pointers must stay valid while the plan is used.
+ * cfg (may be NULL) sets only the work-group size: cfg->block, a multiple
+ * of 64 up to 512 (default 256); other fields are ignored.
  * A persistent work-queue kernel (a machine-sized grid drawing items from an
  * atomic counter) is used instead when BWLA_ENABLE_UNVALIDATED_BATCH=1 is set
  * at plan creation; its current form has not been validated on hardware. */

@@ -901,6 +901,8 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         return fail(BWLA_ERR_INVALID_ARG, "bad descriptor arrays");
     if (cfg && (st = check_cfg(*cfg)) != BWLA_OK)
         return st;
+    if (cfg && cfg->block > 512)
+        return fail(BWLA_ERR_INVALID_ARG, "batch work-groups hold at most 512 threads (block %d)", cfg->block);
     const size_t es = dsize(t), os = out_t == BWLA_F64 ? 8 : 4;
     bool aligned = true;
     const int nv = native_vec(t);

@@ -125,11 +125,20 @@ __global__ __launch_bounds__(1024) void k_batched(BatchArgs a)
 // largest-first queue would -- without a software loop over items, without
 // atomics, and with barriers only in straight-line code.
 // ---------------------------------------------------------------------------
+// Rows of one GEMV tile, one G-lane group per row as in gemv_tile, but each
+// group carries kTileRowsInFlight rows at once and each lane kTilePacksInFlight
+// packs of each row, so that one trip issues all their loads (and the shared
+// packs of x) before any arithmetic.  Loop control is wave-uniform; rows past
+// the tile re-read its last row and are not stored.  No barriers.
+constexpr int kTileRowsInFlight = 4;
+constexpr int kTilePacksInFlight = 2;
+
 template <typename T, int V, bool COMP>
 __device__ __forceinline__ void gemv_tile_block(const BatchGemv &g, int64_t rb, int64_t re, int out_f64)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    constexpr int RB = kTileRowsInFlight, U = kTilePacksInFlight;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int G = g.lanes;
     const int rpw = 64 / G;
@@ -137,49 +146,97 @@ __device__ __forceinline__ void gemv_tile_block(const BatchGemv &g, int64_t rb, 
     const T *A = (const T *)g.A;
     const T *x = (const T *)g.x;
     const int64_t K = g.n, kpack = K / V;
-    for (int64_t base = rb + (int64_t)wave * rpw; base < re; base += (int64_t)nw * rpw) {
-        const int64_t r = base + sub;
-        const int64_t rr = r < re ? r : re - 1;
-        const T *row = A + rr * g.lda;
-        Acc<C, COMP> acc;
-        for (int64_t p = gl; p < kpack; p += G) {
-            Pack<T, V> av = load_pack_nt<T, V>(row + p * V), xv = load_pack<T, V>(x + p * V);
+    const int64_t slots = (int64_t)nw * rpw; // rows the work-group holds per row batch
+    for (int64_t base = rb + (int64_t)wave * rpw; base < re; base += RB * slots) {
+        const T *row[RB];
 #pragma unroll
-            for (int e = 0; e < V; ++e)
-                acc.template add_prod<EXACT>(widen(av.v[e]), widen(xv.v[e]));
+        for (int j = 0; j < RB; ++j) {
+            const int64_t r = base + j * slots + sub;
+            row[j] = A + (r < re ? r : re - 1) * g.lda;
         }
-        for (int64_t k = kpack * V + gl; k < K; k += G)
-            acc.template add_prod<EXACT>(widen(row[k]), widen(x[k]));
-        DD d = acc.to_dd();
-        for (int m = G >> 1; m >= 1; m >>= 1)
-            d = combine<COMP>(d, shfl_xor_dd(d, m));
-        if (gl == 0 && r < re)
-            store_out(g.y, r, out_f64, d.hi + d.lo);
+        Acc<C, COMP> acc[RB];
+        int64_t p = gl;
+        for (; p + (int64_t)(U - 1) * G < kpack; p += (int64_t)U * G) {
+            Pack<T, V> xv[U], av[RB][U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                xv[u] = load_pack<T, V>(x + (p + (int64_t)u * G) * V);
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    av[j][u] = load_pack_nt<T, V>(row[j] + (p + (int64_t)u * G) * V);
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        acc[j].template add_prod<EXACT>(widen(av[j][u].v[e]), widen(xv[u].v[e]));
+        }
+        for (; p < kpack; p += G) {
+            const Pack<T, V> xv = load_pack<T, V>(x + p * V);
+            Pack<T, V> av[RB];
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                av[j] = load_pack_nt<T, V>(row[j] + p * V);
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    acc[j].template add_prod<EXACT>(widen(av[j].v[e]), widen(xv.v[e]));
+        }
+        for (int64_t k = kpack * V + gl; k < K; k += G) {
+            const C xk = widen(x[k]);
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                acc[j].template add_prod<EXACT>(widen(row[j][k]), xk);
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            DD d = acc[j].to_dd();
+            for (int m = G >> 1; m >= 1; m >>= 1)
+                d = combine<COMP>(d, shfl_xor_dd(d, m));
+            const int64_t r = base + j * slots + sub;
+            if (gl == 0 && r < re)
+                store_out(g.y, r, out_f64, d.hi + d.lo);
+        }
     }
 }
+
+// One dot chunk reduced by a whole work-group: each thread keeps
+// kChunkPacksInFlight packs of both operands in flight per trip, two
+// accumulators, then the work-group tree (block_sum, barriers in
+// straight-line code).
+constexpr int kChunkPacksInFlight = 8;
 
 template <typename T, int V, bool COMP>
 __device__ __forceinline__ void dot_chunk_block(const BatchArgs &a, const BatchItem &w, DD *lds)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    constexpr int U = kChunkPacksInFlight;
     const BatchDot &d = a.dots[w.prob];
     const T *x = (const T *)d.x, *y = (const T *)d.y;
     Acc<C, COMP> acc[2];
     const int64_t pb = w.begin / V, pe = w.end / V; // chunk starts are pack-aligned
+    const int64_t step = blockDim.x;
     int64_t p = pb + threadIdx.x;
-    for (; p + blockDim.x < pe; p += 2 * (int64_t)blockDim.x) {
-        Pack<T, V> x0 = load_pack_nt<T, V>(x + p * V), y0 = load_pack_nt<T, V>(y + p * V);
-        Pack<T, V> x1 = load_pack_nt<T, V>(x + (p + blockDim.x) * V);
-        Pack<T, V> y1 = load_pack_nt<T, V>(y + (p + blockDim.x) * V);
+    for (; p + (U - 1) * step < pe; p += U * step) {
+        Pack<T, V> xs[U], ys[U];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            acc[0].template add_prod<EXACT>(widen(x0.v[e]), widen(y0.v[e]));
-            acc[1].template add_prod<EXACT>(widen(x1.v[e]), widen(y1.v[e]));
+        for (int u = 0; u < U; ++u) {
+            xs[u] = load_pack_nt<T, V>(x + (p + u * step) * V);
+            ys[u] = load_pack_nt<T, V>(y + (p + u * step) * V);
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                acc[u & 1].template add_prod<EXACT>(widen(xs[u].v[e]), widen(ys[u].v[e]));
     }
-    for (; p < pe; p += blockDim.x) {
-        Pack<T, V> x0 = load_pack_nt<T, V>(x + p * V), y0 = load_pack_nt<T, V>(y + p * V);
+    for (; p < pe; p += step) {
+        const Pack<T, V> x0 = load_pack_nt<T, V>(x + p * V), y0 = load_pack_nt<T, V>(y + p * V);
 #pragma unroll
         for (int e = 0; e < V; ++e)
             acc[0].template add_prod<EXACT>(widen(x0.v[e]), widen(y0.v[e]));
@@ -197,7 +254,7 @@ __device__ __forceinline__ void dot_chunk_block(const BatchArgs &a, const BatchI
 }
 
 template <typename T, int V, bool COMP>
-__global__ __launch_bounds__(1024) void k_grouped(BatchArgs a)
+__global__ __launch_bounds__(512) void k_grouped(BatchArgs a)
 {
     __shared__ DD lds[16];
     const BatchItem w = a.items[blockIdx.x];

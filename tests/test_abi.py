@@ -158,6 +158,9 @@ def test_batch_plan_validation(L):
     d = (L.DotDesc * 1)(L.DotDesc(FAKE, FAKE, 10, None))
     assert lib.bwla_batch_plan_create(0, 0, 0, g, 0, d, 1, None, ctypes.byref(h)) == L.ERR_INVALID_ARG
     assert lib.bwla_batch_plan_create(0, 0, 1, g, 0, d, 0, None, ctypes.byref(h)) == L.ERR_UNSUPPORTED
+    big = L.Config(block=1024)  # the batched work-groups hold at most 512 threads
+    assert lib.bwla_batch_plan_create(0, 0, 0, g, 0, d, 0, ctypes.byref(big), ctypes.byref(h)) == L.ERR_INVALID_ARG
+    assert "512" in lib.bwla_last_error().decode()
     assert lib.bwla_batch_run(None, None) == L.ERR_INVALID_ARG
     assert lib.bwla_batch_replay(None, None) == L.ERR_INVALID_ARG
 

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 SHAPES = [(1, 1), (1, 7), (7, 1), (33, 65), (257, 1023), (1000, 3001), (64, 20000), (5000, 40)]
 ROWS_CFG = [dict(block=64, vec=1, rows=1, split=1), dict(block=128, vec=2, rows=2, split=3),
             dict(block=256, vec=4, rows=8, split=1), dict(block=1024, vec=4, rows=4, split=2),
-            dict(block=512, vec=2, rows=32, split=7)]
+            dict(block=512, vec=2, rows=8, split=7)]
 COLS_CFG = [dict(block=64, vec=1, unroll=1, split=1), dict(block=128, vec=2, unroll=2, split=3),
             dict(block=256, vec=4, unroll=4, split=1), dict(block=1024, vec=4, unroll=4, split=2),
             dict(block=512, vec=2, unroll=1, split=9)]
