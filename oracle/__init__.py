@@ -21,6 +21,12 @@ Operation definitions follow Section 2 of the paper:
 * ``gemv_dot`` y <- op(A) x stored in the storage precision, then <w, y>: the
   GEMV-then-inner-product pair of a conjugate-gradient iteration, a composite
   of the two definitions above
+* ``scal``   x <- alpha*y, one rounding    (BLAS scal)
+* ``asum``   sum |x_i|                     (BLAS asum, Sum2 compensated evaluation)
+* ``strided`` / ``scatter``  the BLAS increment convention for vectors
+* ``gemv_axpby``  y <- alpha op(A) x + beta y as the composite of ``gemv``,
+  rounding to the output precision, and ``axpby`` (``scal`` when beta == 0,
+  so that y is not read)
 """
 from __future__ import annotations
 
@@ -76,6 +82,10 @@ def _load():
     lib.o_gemv.restype = None
     lib.o_ger.argtypes = [c_int, c_int, i64, i64, dp, dp, dp, i64]
     lib.o_ger.restype = None
+    lib.o_scal.argtypes = [c_int, i64, dbl, dp, dp]
+    lib.o_scal.restype = None
+    lib.o_asum.argtypes = [i64, dp, i64]
+    lib.o_asum.restype = dbl
     _lib = lib
     return lib
 
@@ -167,6 +177,61 @@ def gemv_dot(prec, A, x, w, layout: int = ROW_MAJOR, trans: int = 0, m: int | No
     if prec_code(prec) == F32:
         y = y.astype(np.float32).astype(np.float64)  # round to nearest even
     return y, dot(w, y)
+
+
+def _positions(n: int, inc: int) -> np.ndarray:
+    """Buffer positions of the n logical elements of a strided vector, in the
+    reference-BLAS convention: element i sits at i*inc for inc >= 0 and at
+    (n-1-i)*|inc| for inc < 0 (a negative increment walks the buffer
+    backwards from its end); inc == 0 repeats position 0."""
+    i = np.arange(n, dtype=np.int64)
+    return i * inc if inc >= 0 else (n - 1 - i) * (-inc)
+
+
+def strided(buf, n: int, inc: int) -> np.ndarray:
+    """The n logical elements of the strided vector (buf, inc)."""
+    return np.asarray(buf, dtype=np.float64)[_positions(n, inc)]
+
+
+def scatter(buf, vals, inc: int) -> np.ndarray:
+    """A copy of ``buf`` with the logical elements of (buf, inc) replaced by
+    ``vals``; every other entry is untouched."""
+    out = np.array(buf, dtype=np.float64, copy=True)
+    out[_positions(len(vals), inc)] = vals
+    return out
+
+
+def scal(prec, alpha: float, y) -> np.ndarray:
+    """x = RN(alpha * y) elementwise; alpha is the effective factor."""
+    y = _arr(y)
+    x = np.empty_like(y)
+    _load().o_scal(prec_code(prec), y.size, float(alpha), _ptr(y), _ptr(x))
+    return x
+
+
+def asum(x) -> float:
+    x = _arr(x)
+    return _load().o_asum(x.size, _ptr(x), 1)
+
+
+def gemv_axpby(out_prec, alpha: float, A, x, beta: float, y, layout: int = ROW_MAJOR,
+               trans: int = 0, m: int | None = None, n: int | None = None,
+               lda: int | None = None) -> np.ndarray:
+    """y <- alpha op(A) x + beta y with float64 or float32 output: the
+    GEMV result rounded to ``out_prec`` (as stored), then
+    RN(alpha s_i + RN(beta y_i)) in that precision -- or RN(alpha s_i) when
+    beta == 0, where y is not read.  alpha and beta are rounded to the output
+    precision first."""
+    code = prec_code(out_prec)
+    if code not in (F64, F32):
+        raise ValueError("GEMV output is float64 or float32")
+    s = gemv(A, x, layout, trans, m, n, lda)
+    if code == F32:
+        s = s.astype(np.float32).astype(np.float64)
+    a = scalar(out_prec, alpha)
+    if beta == 0.0:
+        return scal(out_prec, a, s)
+    return axpby(out_prec, a, s, scalar(out_prec, beta), _arr(y))
 
 
 def ger(prec, u, v, layout: int = ROW_MAJOR, lda: int | None = None) -> np.ndarray:

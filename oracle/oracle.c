@@ -112,6 +112,22 @@ void o_axpby(int prec, int64_t n, double alpha, const double *y,
     }
 }
 
+/* ---- scaling x <- alpha*y (the BLAS scal operation) ------------------------
+ * One product per element, rounded once to the storage precision.  Unlike
+ * alpha*y + 0*z there is no 0*y_i term, so infinite and NaN entries scale as
+ * IEEE products do. */
+void o_scal(int prec, int64_t n, double alpha, const double *y, double *x)
+{
+    if (prec == O_F64) {
+        for (int64_t i = 0; i < n; ++i)
+            x[i] = alpha * y[i];
+        return;
+    }
+    float a = (float)alpha;
+    for (int64_t i = 0; i < n; ++i)
+        x[i] = o_store32(prec, a * (float)y[i]);
+}
+
 /* ---- error-free transformations ----------------------------------------- */
 /* Knuth's TwoSum: s + e == a + b exactly, s = RN(a + b). */
 static void two_sum(double a, double b, double *s, double *e)
@@ -134,7 +150,9 @@ static void two_prod(double a, double b, double *p, double *e)
  * Sum of x_i * y_i over n entries with strides incx, incy, evaluated with
  * Dot2 (Ogita, Rump, Oishi 2005): the running sum p is carried with its
  * exact error, the product errors and sum errors are gathered in s, and p + s
- * is the result. */
+ * is the result.  The error terms are meaningless once the running sum is
+ * infinite or NaN (they become inf - inf); the IEEE value of the sum is then
+ * the running sum itself, which is returned. */
 double o_dot(int64_t n, const double *x, int64_t incx, const double *y,
              int64_t incy)
 {
@@ -148,7 +166,25 @@ double o_dot(int64_t n, const double *x, int64_t incx, const double *y,
         two_sum(p, h, &p, &q);
         s = s + (q + r);
     }
-    return p + s;
+    return isfinite(p) ? p + s : p;
+}
+
+/* ---- sum of magnitudes sum |x_i| (the BLAS asum operation) ----------------
+ * Evaluated with Sum2 (Ogita, Rump, Oishi 2005, Algorithm 4.4): the running
+ * sum carries its exact TwoSum errors, which are added at the end; the
+ * result is as accurate as if summed in twice the working precision.  A
+ * non-finite running sum is returned as it is (as for the inner product). */
+double o_asum(int64_t n, const double *x, int64_t incx)
+{
+    if (n <= 0)
+        return 0.0;
+    double p = fabs(x[0]), s = 0.0;
+    for (int64_t i = 1; i < n; ++i) {
+        double q;
+        two_sum(p, fabs(x[i * incx]), &p, &q);
+        s = s + q;
+    }
+    return isfinite(p) ? p + s : p;
 }
 
 /* ---- Euclidean norm: square root of <x, x>, without scaling -------------- */

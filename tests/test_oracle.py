@@ -187,6 +187,20 @@ def test_dot_closed_forms(n):
     assert oracle.dot(alt, ones) == (n % 2)
 
 
+def test_dot_and_nrm2_with_infinite_and_nan_entries():
+    """The IEEE value of a sum with an infinite term is that infinity (NaN
+    for inf - inf or a NaN term); the compensation terms must not turn it
+    into NaN."""
+    x = np.array([1.0, np.inf, 2.0])
+    y = np.array([3.0, 1.0, -1.0])
+    assert oracle.dot(x, y) == np.inf
+    assert oracle.dot(x, -y) == -np.inf
+    assert oracle.nrm2(x) == np.inf
+    assert np.isnan(oracle.dot(np.array([np.inf, -np.inf]), np.ones(2)))
+    assert np.isnan(oracle.dot(np.array([1.0, np.nan]), np.ones(2)))
+    assert oracle.dot(np.array([1e300, 1e300]), np.array([1e10, 1e10])) == np.inf  # overflow
+
+
 def test_dot_empty_and_strided():
     assert oracle.dot([], []) == 0.0
     lib = oracle._load()
@@ -434,3 +448,106 @@ def test_gemv_adjoint_identity_and_finite_differences():
         E[i, j] = h
         fd = (L(A + E, x) - L(A - E, x)) / (2 * h)
         assert abs(fd - dA2[i, j]) <= 1e-8 * (1 + abs(fd))
+
+
+# --------------------------------------------------------------------------
+# BLAS-interface additions: increments, scal, asum, alpha/beta GEMV
+# --------------------------------------------------------------------------
+
+def test_strided_positions_follow_the_blas_convention():
+    """Checked against numpy slicing: a negative increment walks the buffer
+    backwards from its end, a zero increment repeats the first entry."""
+    buf = np.arange(20, dtype=np.float64) * 1.5
+    assert oracle.strided(buf, 10, 2).tolist() == buf[::2][:10].tolist()
+    assert oracle.strided(buf, 20, -1).tolist() == buf[::-1].tolist()
+    assert oracle.strided(buf, 7, -3).tolist() == buf[::3][:7][::-1].tolist()
+    assert oracle.strided(buf, 5, 0).tolist() == [buf[0]] * 5
+    assert oracle.strided(buf, 0, 4).size == 0
+    for inc in (1, 2, -2, 3):
+        n = (20 - 1) // abs(inc) + 1
+        v = oracle.strided(buf, n, inc)
+        assert oracle.scatter(buf, v, inc).tolist() == buf.tolist()
+    out = oracle.scatter(np.zeros(9), np.array([1.0, 2.0, 3.0]), -4)
+    assert out.tolist() == [3.0, 0, 0, 0, 2.0, 0, 0, 0, 1.0]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_scal_single_rounding(prec):
+    rng = np.random.default_rng(91)
+    y = _vals(prec, 300, 92)
+    for alpha in (0.7, -3.25, 1e-3):
+        a = oracle.scalar(prec, alpha)
+        x = oracle.scal(prec, a, y)
+        for xi, yi in zip(x, y):
+            exact = Fraction(a) * Fraction(float(yi))
+            ref = rn(exact, "f64") if prec == "f64" else rn(rn(exact, "f32"), prec)
+            assert Fraction(float(xi)) == ref
+    del rng
+
+
+def test_scal_ieee_specials_differ_from_axpby_with_zero_beta():
+    y = np.array([np.inf, -np.inf, np.nan, -0.0, 0.0, 1.0])
+    x = oracle.scal("f64", 2.0, y)
+    assert x[0] == np.inf and x[1] == -np.inf and np.isnan(x[2])
+    assert math.copysign(1.0, x[3]) == -1.0 and math.copysign(1.0, x[4]) == 1.0 and x[5] == 2.0
+    # axpby with beta = 0 forms 0 * z, which is NaN for an infinite z
+    assert np.isnan(oracle.axpby("f64", 2.0, y, 0.0, y)[0])
+    assert np.isnan(oracle.scal("f32", 0.0, np.array([np.inf]))[0])  # 0 * inf is NaN
+
+
+def test_asum_against_fsum_and_special_cases():
+    """math.fsum is the correctly rounded sum; Sum2's error is at most
+    u |s| + gamma_{n-1}^2 sum |x_i| (Ogita, Rump, Oishi 2005), i.e. about one
+    rounding for terms of one sign."""
+    rng = np.random.default_rng(93)
+    for n in (1, 2, 17, 1000, 100000):
+        x = rng.standard_normal(n) * np.exp(rng.uniform(-20, 20, n))
+        ref = math.fsum(np.abs(x))
+        u = 2.0 ** -53
+        g = (n - 1) * u / (1 - (n - 1) * u)
+        assert abs(oracle.asum(x) - ref) <= u * ref + g * g * ref
+    x = rng.integers(-1000, 1000, 5000).astype(np.float64)
+    assert oracle.asum(x) == float(np.abs(x).sum())  # integers: exact
+    assert oracle.asum(np.array([])) == 0.0
+    assert oracle.asum(np.array([-np.inf, 1.0])) == np.inf
+    assert np.isnan(oracle.asum(np.array([np.nan, 1.0])))
+    # a sum that plain double accumulation gets wrong: 1 + 2^-53 (many times)
+    x = np.array([1.0] + [2.0 ** -53] * 1000)
+    assert oracle.asum(x) == math.fsum(x) == 1.0 + 1000 * 2.0 ** -53
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("trans", [0, 1])
+def test_gemv_axpby_small_integers_exact(layout, trans):
+    rng = np.random.default_rng(94 + trans)
+    m, n = 11, 7
+    A = rng.integers(-5, 6, (m, n)).astype(np.float64)
+    x = rng.integers(-5, 6, m if trans else n).astype(np.float64)
+    y = rng.integers(-5, 6, n if trans else m).astype(np.float64)
+    flat, lda = _flat(A, layout, pad=1)
+    B = A.T if trans else A
+    for prec in ("f64", "f32"):
+        got = oracle.gemv_axpby(prec, 2.0, flat, x, -3.0, y, layout=layout, trans=trans, m=m, n=n, lda=lda)
+        assert got.tolist() == (2.0 * (B @ x) - 3.0 * y).tolist()
+        # beta == 0: y is not read (a NaN there does not propagate)
+        got = oracle.gemv_axpby(prec, -1.5, flat, x, 0.0, np.full(y.size, np.nan), layout=layout,
+                                trans=trans, m=m, n=n, lda=lda)
+        assert got.tolist() == (-1.5 * (B @ x)).tolist()
+    with pytest.raises(ValueError):
+        oracle.gemv_axpby("bf16", 1.0, A, x, 0.0, y)
+
+
+def test_gemv_axpby_rounding_sequence():
+    """f32 output: the product is rounded to float32 before the update.
+    s = 1 + 2^-30 is stored as 1; then 1 + RN(1 * 2^-24) is a tie that rounds
+    to the even 1.  In float64 the terms survive."""
+    A = np.array([[1.0, 2.0 ** -30]])
+    got = oracle.gemv_axpby("f32", 1.0, A, np.ones(2), 1.0, np.array([2.0 ** -24]))
+    assert got.tolist() == [1.0]
+    got = oracle.gemv_axpby("f64", 1.0, A, np.ones(2), 1.0, np.array([2.0 ** -24]))
+    assert got.tolist() == [1.0 + 2.0 ** -30 + 2.0 ** -24]
+    # alpha is rounded to float32 first: 0.1 -> 0x3dcccccd
+    a32 = float(np.float32(0.1))
+    got = oracle.gemv_axpby("f32", 0.1, np.array([[3.0]]), np.ones(1), 0.0, np.zeros(1))
+    assert got[0] == float(np.float32(a32 * 3.0))
+
