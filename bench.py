@@ -193,6 +193,28 @@ def extra_rows(torch, W, ops, reps):
     rate("composite gemv 8192^2 + dot f64 fused epilogue (same work)", (m * m + 3 * m) * 8,
          lambda: composite.gemv_dot_fused(A, pv, q=q))
     del A
+    # BLAS-interface additions (float64): scal and asum at unit increment;
+    # strided vectors (bytes = the elements used, the lines in between are
+    # fetched too); alpha/beta GEMV against the plain one
+    n = 1 << 26
+    a = W.device_draw(n, "f64", 0, 940)
+    b = W.device_draw(n, "f64", 0, 941)
+    rate("blas scal f64 n=2^26", 2 * n * 8, lambda: ops.scal(1.0000001, a))
+    for acc in ("plain", "compensated"):
+        rate("blas asum f64 %s n=2^26" % acc, n * 8, lambda acc=acc: ops.asum(a, acc=acc))
+    h = n // 2
+    rate("blas dot f64 inc=2 n=2^25 (elements used)", 2 * h * 8, lambda: ops.dot(a[::2], b[::2]))
+    rate("blas axpby f64 inc=2 n=2^25 (elements used)", 3 * h * 8,
+         lambda: ops.axpby(0.5, a[::2], 0.25, b[::2], out=b[::2]))
+    del a, b
+    m = 16384
+    A = W.device_draw(m * m, "f64", 0, 942).view(m, m)
+    x = W.device_draw(m, "f64", 0, 943)
+    y = W.device_draw(m, "f64", 0, 944)
+    rate("blas gemv f64 16384^2 y = A x", (m * m + 2 * m) * 8, lambda: ops.gemv(A, x, out=y))
+    rate("blas gemv f64 16384^2 y = 0.5 A x + 2 y", (m * m + 3 * m) * 8,
+         lambda: ops.gemv(A, x, out=y, alpha=0.5, beta=2.0))
+    del A
     return out
 
 

@@ -135,6 +135,42 @@ bwla_status bwla_dot(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const
 bwla_status bwla_nrm2(bwla_dtype t, bwla_acc acc, int64_t n, const void *x,
                       bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- vectors with an increment ----------------------------------------------
+ * The paper's Section 2 builds the level-1 and level-2 BLAS from these
+ * operations and notes that its vector data types suit strided vectors
+ * poorly; these entry points complete the BLAS-style interface.  A vector is
+ * (p, n, inc) in the reference-BLAS convention: logical element i is at
+ * p[i*inc] for inc >= 0 and at p[(n-1-i)*|inc|] for inc < 0 (a negative
+ * increment walks the buffer backwards from its far end).  inc == 0 repeats
+ * p[0] and is allowed for inputs only.  Arithmetic and rounding are exactly
+ * those of the unit-increment operation; with every increment 1 the call is
+ * the unit-increment one (packed kernels).  Otherwise each element is moved
+ * on its own (no 16-byte packs across a stride).  An output may alias an
+ * input exactly (same pointer and increment); any other shared byte is an
+ * error (interleaved vectors with equal |inc| that share no element are
+ * fine).  (n - 1) * |inc| * element size must stay below 2^60. */
+bwla_status bwla_copy_strided(bwla_dtype t, int64_t n, const void *y, int64_t incy, void *x,
+                              int64_t incx, void *stream);
+bwla_status bwla_axpby_strided(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev,
+                               const void *y, int64_t incy, double beta, const void *beta_dev,
+                               const void *z, int64_t incz, void *x, int64_t incx, void *stream);
+/* x <- alpha x in place (the BLAS scal): x_i = RN_t(a * x_i) with a the
+ * effective factor as in bwla_axpby.  One product per element, so infinite
+ * and NaN entries scale as IEEE products do (unlike axpby with beta = 0,
+ * which forms 0 * z). */
+bwla_status bwla_scal(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev, void *x,
+                      int64_t incx, void *stream);
+/* Reductions with increments; workspace as for bwla_dot (bwla_workspace_size
+ * with BWLA_OP_DOT, BWLA_OP_NRM2 or BWLA_OP_CG serves every increment). */
+bwla_status bwla_dot_strided(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, int64_t incx,
+                             const void *y, int64_t incy, bwla_dtype out_t, void *out, void *ws,
+                             size_t ws_bytes, void *stream);
+bwla_status bwla_nrm2_strided(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, int64_t incx,
+                              bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream);
+/* out <- sum |x_i| (the BLAS asum), reduced as bwla_nrm2 reduces x_i^2. */
+bwla_status bwla_asum(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, int64_t incx,
+                      bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- dense matrix-vector product: y <- op(A) x (paper Section 2) ----------
  * A is m x n.  Row-major: A_ij at A[i*lda + j], lda >= max(1, n).
  * Column-major: A_ij at A[i + j*lda], lda >= max(1, m).
@@ -173,6 +209,22 @@ bwla_status bwla_gemv_dot(bwla_dtype t, bwla_acc acc, bwla_layout layout, int tr
 bwla_status bwla_gemv_dot_workspace_size(bwla_dtype t, bwla_layout layout, int trans, int64_t m,
                                          int64_t n, size_t *bytes);
 
+/* ---- y <- alpha op(A) x + beta y with increments (the BLAS gemv) -----------
+ * Defined as the composite: s = op(A) x exactly as bwla_gemv stores it in
+ * out_t, then y_i <- RN(fma(a, s_i, RN(b y_i))) in out_t's precision (as
+ * bwla_axpby), or y_i <- RN(a s_i) when beta == 0, in which case y is not
+ * read.  a, b: alpha, beta rounded to out_t.  x is (x, in_len, incx) and y
+ * is (y, out_len, incy) in the increment convention above (incy != 0).
+ * alpha == 1, beta == 0 with unit increments is bwla_gemv itself; otherwise
+ * s goes through the workspace (and a strided x is gathered there first),
+ * at least bwla_gemv_ex_workspace_size() bytes.  y must not overlap A or x. */
+bwla_status bwla_gemv_ex(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m,
+                         int64_t n, double alpha, const void *A, int64_t lda, const void *x,
+                         int64_t incx, double beta, bwla_dtype out_t, void *y, int64_t incy,
+                         void *ws, size_t ws_bytes, void *stream);
+bwla_status bwla_gemv_ex_workspace_size(bwla_dtype t, bwla_dtype out_t, bwla_layout layout, int trans,
+                                        int64_t m, int64_t n, size_t *bytes);
+
 /* ---- rank-1 overwrite: A <- u v^T ------------------------------------------
  * The gradient of y = A x with respect to A for an incoming gradient u = ybar
  * and v = x.  A is m x n in the given layout and leading dimension; every
@@ -196,7 +248,8 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha,
 /* Bytes of workspace that the call with these arguments needs under the
  * current configuration table.  `op` is the public operation: BWLA_OP_DOT,
  * BWLA_OP_NRM2 or BWLA_OP_CG (m ignored, n = length; any of the three gives
- * a size that serves all three), BWLA_OP_GEMV_ROWS or BWLA_OP_GEMV_COLS for
+ * a size that serves all three, bwla_asum and every increment),
+ * BWLA_OP_GEMV_ROWS or BWLA_OP_GEMV_COLS for
  * bwla_gemv (either is accepted: the kernel is chosen from layout and
  * trans). */
 bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_layout layout,

@@ -54,6 +54,15 @@ SIGNATURES = {
     "bwla_gemv_dot": (c_int, [c_int, c_int, c_int, c_int, i64, i64, vp, i64, vp, vp, vp, c_int, vp, vp,
                               sz, vp]),
     "bwla_gemv_dot_workspace_size": (c_int, [c_int, c_int, c_int, i64, i64, ctypes.POINTER(sz)]),
+    "bwla_copy_strided": (c_int, [c_int, i64, vp, i64, vp, i64, vp]),
+    "bwla_axpby_strided": (c_int, [c_int, i64, dbl, vp, vp, i64, dbl, vp, vp, i64, vp, i64, vp]),
+    "bwla_scal": (c_int, [c_int, i64, dbl, vp, vp, i64, vp]),
+    "bwla_dot_strided": (c_int, [c_int, c_int, i64, vp, i64, vp, i64, c_int, vp, vp, sz, vp]),
+    "bwla_nrm2_strided": (c_int, [c_int, c_int, i64, vp, i64, c_int, vp, vp, sz, vp]),
+    "bwla_asum": (c_int, [c_int, c_int, i64, vp, i64, c_int, vp, vp, sz, vp]),
+    "bwla_gemv_ex": (c_int, [c_int, c_int, c_int, c_int, i64, i64, dbl, vp, i64, vp, i64, dbl, c_int, vp, i64,
+                             vp, sz, vp]),
+    "bwla_gemv_ex_workspace_size": (c_int, [c_int, c_int, c_int, c_int, i64, i64, ctypes.POINTER(sz)]),
     "bwla_ger": (c_int, [c_int, c_int, i64, i64, vp, vp, vp, i64, vp]),
     "bwla_cg_update": (c_int, [c_int, c_int, i64, dbl, vp, vp, vp, vp, vp, c_int, vp, vp, sz, vp]),
     "bwla_workspace_size": (c_int, [c_int, c_int, c_int, c_int, c_int, i64, i64, ctypes.POINTER(sz)]),

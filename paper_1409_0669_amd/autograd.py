@@ -35,7 +35,7 @@ class GemvFn(torch.autograd.Function):
             dx = ops.gemv(A, ybar, trans=True, acc=ctx.acc, out_dtype=A.dtype)
         if ctx.needs_input_grad[0]:
             dA = torch.empty_strided(A.shape, A.stride(), dtype=A.dtype, device=A.device)
-            ops.ger(ybar, x, dA)
+            ops.ger(ybar, x.contiguous(), dA)  # the rank-1 kernel reads unit-stride vectors
         return dA, dx, None
 
 

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libbwla.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-KERNEL_SOURCES = ("stream.hip", "reduce.hip", "gemv.hip", "ger.hip", "batched.hip")
+KERNEL_SOURCES = ("stream.hip", "reduce.hip", "gemv.hip", "ger.hip", "batched.hip", "strided.hip")
 TYPES = {"f64": "double", "f32": "float", "bf16": "__bf16"}
 
 COMMON_FLAGS = [

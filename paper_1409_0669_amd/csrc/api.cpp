@@ -360,6 +360,51 @@ bwla_status check_reduction(int t, int acc, int64_t n, int out_t, void *out, voi
     return BWLA_OK;
 }
 
+// --- vectors with an increment ------------------------------------------------
+uint64_t uabs(int64_t v) { return v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v; }
+
+// Bytes from the lowest to the highest element of (p, n, inc), one element
+// included.
+Span sspan(const void *p, int64_t n, int64_t inc, size_t es)
+{
+    if (n <= 0)
+        return Span{(uintptr_t)p, (uintptr_t)p};
+    return span(p, (size_t)((uint64_t)(n - 1) * uabs(inc) + 1) * es);
+}
+
+// True when no byte is shared.  Overlapping spans with the same nonzero |inc|
+// can still interleave: their elements are then at least one element apart
+// modulo the stride.
+bool sdisjoint(const void *a, int64_t inca, const void *b, int64_t incb, int64_t n, size_t es)
+{
+    if (!overlaps(sspan(a, n, inca, es), sspan(b, n, incb, es)))
+        return true;
+    if (uabs(inca) != uabs(incb) || inca == 0)
+        return false;
+    const uint64_t S = uabs(inca) * es;
+    const uint64_t d = (uintptr_t)a > (uintptr_t)b ? (uintptr_t)a - (uintptr_t)b : (uintptr_t)b - (uintptr_t)a;
+    const uint64_t r = d % S;
+    return r >= es && S - r >= es;
+}
+
+// (n - 1) * |inc| * es stays far inside the address space.
+bool sfits(int64_t n, int64_t inc, size_t es)
+{
+    return n <= 1 || uabs(inc) <= ((uint64_t)1 << 60) / es / (uint64_t)(n - 1);
+}
+
+int strided_grid(int64_t n, bool reduction)
+{
+    const int64_t per = (int64_t)kStridedBlock * kStridedUnroll;
+    const int64_t cap = (int64_t)(reduction ? 2 : 8) * device_cus(); // reductions: few partials
+    return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), per), cap));
+}
+size_t ws_strided(int64_t n)
+{
+    const int g = strided_grid(n, true);
+    return g > 1 ? (size_t)g * sizeof(DD) : 0;
+}
+
 } // namespace
 
 // ===========================================================================
@@ -434,41 +479,171 @@ bwla_status bwla_axpby(bwla_dtype t, int64_t n, double alpha, const void *alpha_
     return hip_check(e, "axpby launch");
 }
 
-static bwla_status dot_common(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
-                              bool square, bwla_dtype out_t, void *out, void *ws, size_t ws_bytes,
-                              void *stream)
+// dot (kRedDot), nrm2 (kRedSq) and asum (kRedAbs), any increments.
+static bwla_status reduce_common(bwla_dtype t, bwla_acc acc, int mode, int64_t n, const void *x, int64_t incx,
+                                 const void *y, int64_t incy, bwla_dtype out_t, void *out, void *ws,
+                                 size_t ws_bytes, void *stream)
 {
-    Cfg c = resolve_vector(square ? BWLA_OP_NRM2 : BWLA_OP_DOT, t, n, {x, y}, square ? 1 : 2);
-    const size_t need = n > 0 ? ws_dot(c) : 0;
+    const bool two = mode == kRedDot;
+    const bool packed = incx == 1 && (!two || incy == 1);
+    const size_t es = valid_dtype(t) ? dsize(t) : 1;
+    Cfg c{};
+    size_t need = 0;
+    if (packed) {
+        c = resolve_vector(two ? BWLA_OP_DOT : BWLA_OP_NRM2, t, n, {x, y}, two ? 2 : 1);
+        need = n > 0 ? ws_dot(c) : 0;
+    } else {
+        need = n > 0 ? ws_strided(n) : 0;
+    }
     bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
     if (st)
         return st;
-    if (n > 0 && (!x || (!square && !y)))
+    if (!sfits(n, incx, es) || (two && !sfits(n, incy, es)))
+        return fail(BWLA_ERR_INVALID_ARG, "increment too large for n = %lld", (long long)n);
+    if (n > 0 && (!x || (two && !y)))
         return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
     const size_t os = out_t == BWLA_F64 ? 8 : 4;
     Span so = span(out, os);
-    if (n > 0 && (overlaps(so, span(x, n * dsize(t))) || (!square && overlaps(so, span(y, n * dsize(t))))))
+    if (n > 0 && (overlaps(so, sspan(x, n, incx, es)) || (two && overlaps(so, sspan(y, n, incy, es)))))
         return fail(BWLA_ERR_INVALID_ARG, "out overlaps an input");
+    hipStream_t s = (hipStream_t)stream;
     if (n == 0)
-        return hip_check(launch_fill_zero(out, 1, out_t == BWLA_F64, (hipStream_t)stream), "fill launch");
+        return hip_check(launch_fill_zero(out, 1, out_t == BWLA_F64, s), "fill launch");
+    const bool comp = acc == BWLA_ACC_COMPENSATED;
+    const int of64 = out_t == BWLA_F64;
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
-        return launch_dot<T>(n, acc == BWLA_ACC_COMPENSATED, square, x, square ? x : y,
-                             out_t == BWLA_F64, out, ws, c, (hipStream_t)stream);
+        if (packed)
+            return launch_dot<T>(n, comp, mode, x, two ? y : x, of64, out, ws, c, s);
+        return launch_strided_reduce<T>(mode, n, comp, x, incx, two ? y : x, two ? incy : incx, of64, out, ws,
+                                        strided_grid(n, true), s);
     });
-    return hip_check(e, square ? "nrm2 launch" : "dot launch");
+    return hip_check(e, mode == kRedDot ? "dot launch" : mode == kRedSq ? "nrm2 launch" : "asum launch");
 }
 
 bwla_status bwla_dot(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
                      bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream)
 {
-    return dot_common(t, acc, n, x, y, false, out_t, out, ws, ws_bytes, stream);
+    return reduce_common(t, acc, kRedDot, n, x, 1, y, 1, out_t, out, ws, ws_bytes, stream);
 }
 
 bwla_status bwla_nrm2(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, bwla_dtype out_t,
                       void *out, void *ws, size_t ws_bytes, void *stream)
 {
-    return dot_common(t, acc, n, x, nullptr, true, out_t, out, ws, ws_bytes, stream);
+    return reduce_common(t, acc, kRedSq, n, x, 1, nullptr, 1, out_t, out, ws, ws_bytes, stream);
+}
+
+bwla_status bwla_dot_strided(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, int64_t incx, const void *y,
+                             int64_t incy, bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream)
+{
+    return reduce_common(t, acc, kRedDot, n, x, incx, y, incy, out_t, out, ws, ws_bytes, stream);
+}
+
+bwla_status bwla_nrm2_strided(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, int64_t incx,
+                              bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream)
+{
+    return reduce_common(t, acc, kRedSq, n, x, incx, nullptr, 1, out_t, out, ws, ws_bytes, stream);
+}
+
+bwla_status bwla_asum(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, int64_t incx, bwla_dtype out_t,
+                      void *out, void *ws, size_t ws_bytes, void *stream)
+{
+    return reduce_common(t, acc, kRedAbs, n, x, incx, nullptr, 1, out_t, out, ws, ws_bytes, stream);
+}
+
+// --- strided elementwise operations ---------------------------------------------
+bwla_status bwla_copy_strided(bwla_dtype t, int64_t n, const void *y, int64_t incy, void *x, int64_t incx,
+                              void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    if (n == 0)
+        return BWLA_OK;
+    const size_t es = dsize(t);
+    if (incx == 0)
+        return fail(BWLA_ERR_INVALID_ARG, "the output increment is 0");
+    if (!sfits(n, incx, es) || !sfits(n, incy, es))
+        return fail(BWLA_ERR_INVALID_ARG, "increment too large for n = %lld", (long long)n);
+    if (incx == 1 && incy == 1)
+        return bwla_copy(t, n, y, x, stream);
+    if (!x || !y)
+        return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
+    if (x == y && incx == incy)
+        return BWLA_OK;
+    if (!sdisjoint(x, incx, y, incy, n, es))
+        return fail(BWLA_ERR_INVALID_ARG, "x overlaps y");
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_strided_elem<T>(kElemCopy, n, 0.0, nullptr, 0.0, nullptr, y, incy, nullptr, 0, x, incx,
+                                      strided_grid(n, false), (hipStream_t)stream);
+    });
+    return hip_check(e, "strided copy launch");
+}
+
+bwla_status bwla_axpby_strided(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev, const void *y,
+                               int64_t incy, double beta, const void *beta_dev, const void *z, int64_t incz,
+                               void *x, int64_t incx, void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    if (n == 0)
+        return BWLA_OK;
+    const size_t es = dsize(t);
+    if (incx == 0)
+        return fail(BWLA_ERR_INVALID_ARG, "the output increment is 0");
+    if (!sfits(n, incx, es) || !sfits(n, incy, es) || !sfits(n, incz, es))
+        return fail(BWLA_ERR_INVALID_ARG, "increment too large for n = %lld", (long long)n);
+    if (incx == 1 && incy == 1 && incz == 1)
+        return bwla_axpby(t, n, alpha, alpha_dev, y, beta, beta_dev, z, x, stream);
+    if (!x || !y || !z)
+        return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
+    if (!(x == y && incx == incy) && !sdisjoint(x, incx, y, incy, n, es))
+        return fail(BWLA_ERR_INVALID_ARG, "x overlaps y (only exact aliasing is allowed)");
+    if (!(x == z && incx == incz) && !sdisjoint(x, incx, z, incz, n, es))
+        return fail(BWLA_ERR_INVALID_ARG, "x overlaps z (only exact aliasing is allowed)");
+    const size_t cs = t == BWLA_F64 ? 8 : 4;
+    Span sx = sspan(x, n, incx, es);
+    if ((alpha_dev && overlaps(sx, span(alpha_dev, cs))) || (beta_dev && overlaps(sx, span(beta_dev, cs))))
+        return fail(BWLA_ERR_INVALID_ARG, "a device scalar lies inside the output x");
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_strided_elem<T>(kElemAxpby, n, alpha, alpha_dev, beta, beta_dev, y, incy, z, incz, x, incx,
+                                      strided_grid(n, false), (hipStream_t)stream);
+    });
+    return hip_check(e, "strided axpby launch");
+}
+
+bwla_status bwla_scal(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev, void *x, int64_t incx,
+                      void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    if (n == 0)
+        return BWLA_OK;
+    const size_t es = dsize(t);
+    if (incx == 0)
+        return fail(BWLA_ERR_INVALID_ARG, "the increment is 0");
+    if (!sfits(n, incx, es))
+        return fail(BWLA_ERR_INVALID_ARG, "increment too large for n = %lld", (long long)n);
+    if (!x)
+        return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
+    if (alpha_dev && overlaps(sspan(x, n, incx, es), span(alpha_dev, t == BWLA_F64 ? 8 : 4)))
+        return fail(BWLA_ERR_INVALID_ARG, "the device scalar lies inside x");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        if (incx == 1) // reads and writes one stream each, as the copy
+            return launch_scal<T>(n, alpha, alpha_dev, x, x, resolve_vector(BWLA_OP_COPY, t, n, {x}, 2), s);
+        return launch_strided_elem<T>(kElemScal, n, alpha, alpha_dev, 0.0, nullptr, x, incx, nullptr, 0, x, incx,
+                                      strided_grid(n, false), s);
+    });
+    return hip_check(e, "scal launch");
 }
 
 // Which kernel serves (layout, trans), and the line view of A.
@@ -628,6 +803,130 @@ bwla_status bwla_gemv_dot_workspace_size(bwla_dtype t, bwla_layout layout, int t
     return BWLA_OK;
 }
 
+// y <- alpha op(A) x + beta y with increments: the GEMV into a contiguous
+// temporary of the workspace, then a strided scal (beta == 0: y is not read)
+// or axpby into y.  A strided x is first gathered into the workspace.
+// Workspace: [x gathered | temporary y | GEMV partials], 256-byte aligned parts.
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bwla_status bwla_gemv_ex(bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans, int64_t m, int64_t n,
+                         double alpha, const void *A, int64_t lda, const void *x, int64_t incx, double beta,
+                         bwla_dtype out_t, void *y, int64_t incy, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (acc != BWLA_ACC_PLAIN && acc != BWLA_ACC_COMPENSATED)
+        return fail(BWLA_ERR_UNSUPPORTED, "accumulation mode %d", acc);
+    if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
+        return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
+    if (trans != 0 && trans != 1)
+        return fail(BWLA_ERR_INVALID_ARG, "trans %d", trans);
+    if (m < 0 || n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "negative size m=%lld n=%lld", (long long)m, (long long)n);
+    bwla_status st = out_type_ok(t, out_t);
+    if (st)
+        return st;
+    GemvPlan g = gemv_plan(layout, trans, m, n);
+    if (lda < std::max<int64_t>(1, g.K))
+        return fail(BWLA_ERR_INVALID_ARG, "lda %lld < %lld", (long long)lda, (long long)std::max<int64_t>(1, g.K));
+    const size_t es = dsize(t), os = out_t == BWLA_F64 ? 8 : 4;
+    if (incy == 0)
+        return fail(BWLA_ERR_INVALID_ARG, "the output increment is 0");
+    if (!sfits(g.out_len, incy, os) || !sfits(g.in_len, incx, es))
+        return fail(BWLA_ERR_INVALID_ARG, "increment too large");
+    if (g.out_len == 0)
+        return BWLA_OK;
+    if (!y)
+        return fail(BWLA_ERR_INVALID_ARG, "y is NULL");
+    if (g.in_len > 0 && (!A || !x))
+        return fail(BWLA_ERR_INVALID_ARG, "NULL A or x with a nonzero reduction length");
+    Span sy = sspan(y, g.out_len, incy, os);
+    if (g.in_len > 0 && (overlaps(sy, span(A, matrix_bytes(g.L, g.K, lda, es))) ||
+                         overlaps(sy, sspan(x, g.in_len, incx, es))))
+        return fail(BWLA_ERR_INVALID_ARG, "y overlaps A or x");
+    if (alpha == 1.0 && beta == 0.0 && incx == 1 && incy == 1)
+        return gemv_common(t, acc, layout, trans, m, n, A, lda, x, out_t, y, nullptr, out_t, nullptr, ws,
+                           ws_bytes, stream);
+    // workspace parts
+    const bool gather = incx != 1 && g.in_len > 0;
+    const size_t off_tmp = align256(gather ? (size_t)g.in_len * es : 0);
+    const size_t off_g = align256(off_tmp + (size_t)g.out_len * os);
+    const void *xs = gather ? ws : x;
+    Cfg c{};
+    size_t need = off_g;
+    if (g.in_len > 0) {
+        c = gemv_cfg(t, g, A, lda, xs);
+        need += gemv_ws(g, c, false, nullptr);
+    }
+    if (!ws || ws_bytes < need)
+        return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    hipStream_t s = (hipStream_t)stream;
+    void *tmp = (char *)ws + off_tmp;
+    void *gws = (char *)ws + off_g;
+    const bool comp = acc == BWLA_ACC_COMPENSATED;
+    const int of64 = out_t == BWLA_F64;
+    hipError_t e = hipSuccess;
+    if (g.in_len == 0) {
+        e = launch_fill_zero(tmp, g.out_len, of64, s);
+    } else {
+        e = by_type(t, [&](auto *tag) {
+            using T = std::remove_pointer_t<decltype(tag)>;
+            hipError_t r = hipSuccess;
+            if (gather)
+                r = launch_strided_elem<T>(kElemCopy, g.in_len, 0.0, nullptr, 0.0, nullptr, x, incx, nullptr, 0,
+                                           ws, 1, strided_grid(g.in_len, false), s);
+            if (r != hipSuccess)
+                return r;
+            if (g.rows)
+                return launch_gemv_rows<T>(g.L, g.K, comp, A, lda, xs, of64, tmp, gws, c, s);
+            return launch_gemv_cols<T>(g.L, g.K, comp, A, lda, xs, of64, tmp, gws, c, s);
+        });
+    }
+    if (e != hipSuccess)
+        return hip_check(e, "gemv_ex launch");
+    e = by_type(out_t, [&](auto *tag) {
+        using O = std::remove_pointer_t<decltype(tag)>;
+        if (beta == 0.0)
+            return launch_strided_elem<O>(kElemScal, g.out_len, alpha, nullptr, 0.0, nullptr, tmp, 1, nullptr, 0,
+                                          y, incy, strided_grid(g.out_len, false), s);
+        return launch_strided_elem<O>(kElemAxpby, g.out_len, alpha, nullptr, beta, nullptr, tmp, 1, y, incy, y,
+                                      incy, strided_grid(g.out_len, false), s);
+    });
+    return hip_check(e, "gemv_ex update launch");
+}
+
+bwla_status bwla_gemv_ex_workspace_size(bwla_dtype t, bwla_dtype out_t, bwla_layout layout, int trans,
+                                        int64_t m, int64_t n, size_t *bytes)
+{
+    if (!bytes)
+        return fail(BWLA_ERR_INVALID_ARG, "bytes is NULL");
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    bwla_status st = out_type_ok(t, out_t);
+    if (st)
+        return st;
+    if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
+        return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
+    if (trans != 0 && trans != 1)
+        return fail(BWLA_ERR_INVALID_ARG, "trans %d", trans);
+    if (m < 0 || n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "negative size");
+    *bytes = 0;
+    GemvPlan g = gemv_plan(layout, trans, m, n);
+    if (g.out_len == 0)
+        return BWLA_OK;
+    const size_t os = out_t == BWLA_F64 ? 8 : 4;
+    size_t best = align256(align256((size_t)g.in_len * dsize(t)) + (size_t)g.out_len * os);
+    size_t gw = 0;
+    if (g.in_len > 0)
+        for (int v = 1; v <= 16; v <<= 1) {
+            const void *fake = (const void *)(uintptr_t)(v * dsize(t));
+            gw = std::max(gw, gemv_ws(g, gemv_cfg(t, g, fake, v, fake), false, nullptr));
+        }
+    *bytes = best + gw;
+    return BWLA_OK;
+}
+
 bwla_status bwla_ger(bwla_dtype t, bwla_layout layout, int64_t m, int64_t n, const void *u, const void *v,
                      void *A, int64_t lda, void *stream)
 {
@@ -706,9 +1005,10 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
     for (int v = 1; v <= 16; v <<= 1) {
         const void *fake = (const void *)(uintptr_t)(v * dsize(t));
         switch (op) {
-        case BWLA_OP_DOT: // dot, nrm2 and the fused CG update share one sizing
+        case BWLA_OP_DOT: // dot, nrm2, asum (any increments) and the CG update share one sizing
         case BWLA_OP_NRM2:
         case BWLA_OP_CG:
+            best = std::max(best, ws_strided(n));
             best = std::max(best, ws_dot(resolve_vector(BWLA_OP_DOT, t, n, {fake}, 2)));
             best = std::max(best, ws_dot(resolve_vector(BWLA_OP_NRM2, t, n, {fake}, 1)));
             best = std::max(best, ws_dot(resolve_vector(kOpCg, t, n, {fake}, 6)));

@@ -182,17 +182,28 @@ template <typename C> __device__ __forceinline__ void fast_two_sum(C a, C b, C &
     e = b - (s - a);
 }
 
+// |a| in the compute precision (clears the sign bit: |-0| = +0).
+__device__ __forceinline__ float abs_c(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double abs_c(double a) { return __builtin_fabs(a); }
+
 // A float64 value carried with its rounding error (hi + lo, |lo| <= ulp(hi)/2).
 struct DD {
     double hi, lo;
 };
 
+// Once the sum is infinite or NaN the error terms are meaningless (inf - inf)
+// and the IEEE value of the sum is the plain sum, which is kept with lo = 0.
 __device__ __forceinline__ DD dd_add(DD a, DD b)
 {
     double s, e;
     two_sum(a.hi, b.hi, s, e);
-    e += a.lo + b.lo;
     DD r;
+    if (!__builtin_isfinite(s)) {
+        r.hi = s;
+        r.lo = 0.0;
+        return r;
+    }
+    e += a.lo + b.lo;
     fast_two_sum(s, e, r.hi, r.lo);
     return r;
 }
@@ -237,6 +248,9 @@ template <typename C, bool COMP> struct Acc {
     {
         DD r;
         if constexpr (!COMP) {
+            r.hi = (double)s;
+            r.lo = 0.0;
+        } else if (!__builtin_isfinite(s)) { // see dd_add
             r.hi = (double)s;
             r.lo = 0.0;
         } else {

@@ -59,6 +59,9 @@ template <typename F> hipError_t with_bool(bool b, F &&f)
 template <typename T>
 hipError_t launch_copy(int64_t n, const void *y, void *x, const Cfg &c, hipStream_t s);
 template <typename T>
+hipError_t launch_scal(int64_t n, double alpha, const void *adev, const void *y, void *x, const Cfg &c,
+                       hipStream_t s);
+template <typename T>
 hipError_t launch_axpby(int64_t n, double alpha, const void *adev, const void *y, double beta,
                         const void *bdev, const void *z, void *x, const Cfg &c, hipStream_t s);
 template <typename T>
@@ -66,11 +69,27 @@ hipError_t launch_cg(int64_t n, bool comp, double alpha, const void *adev, void 
                      void *r, const void *q, int out_f64, void *out, void *ws, const Cfg &c,
                      hipStream_t s);
 
-// --- reductions: dot and nrm2 ----------------------------------------------
+// --- reductions: dot, nrm2, asum (mode kRedDot, kRedSq, kRedAbs) -----------
 // Partials needed: c.grid DD pairs.
 template <typename T>
-hipError_t launch_dot(int64_t n, bool comp, bool square, const void *x, const void *y, int out_f64,
+hipError_t launch_dot(int64_t n, bool comp, int mode, const void *x, const void *y, int out_f64,
                       void *out, void *ws, const Cfg &c, hipStream_t s);
+
+// --- vectors with an increment (BLAS convention; see strided.hip) ----------
+enum { kElemCopy = 0, kElemAxpby = 1, kElemScal = 2 };
+enum { kRedDot = 0, kRedSq = 1, kRedAbs = 2 };
+constexpr int kStridedBlock = 256; // threads per work-group
+constexpr int kStridedUnroll = 4;  // elements in flight per thread
+// x = copy(y) / RN(fma(a, y, RN(b z))) / RN(a y) with a, b the effective
+// factors (host value times *adev / *bdev when given).
+template <typename T>
+hipError_t launch_strided_elem(int mode, int64_t n, double alpha, const void *adev, double beta,
+                               const void *bdev, const void *y, int64_t incy, const void *z, int64_t incz,
+                               void *x, int64_t incx, int grid, hipStream_t s);
+// <x, y>, sqrt(sum x_i^2) or sum |x_i|; `grid` DD partials in ws when grid > 1.
+template <typename T>
+hipError_t launch_strided_reduce(int mode, int64_t n, bool comp, const void *x, int64_t incx, const void *y,
+                                 int64_t incy, int out_f64, void *out, void *ws, int grid, hipStream_t s);
 
 // --- matrix-vector ---------------------------------------------------------
 // A line is a contiguous run of K elements; lines are ld apart.

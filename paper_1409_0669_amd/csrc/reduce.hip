@@ -1,5 +1,6 @@
-// reduce.hip -- inner product <x, y> and Euclidean norm sqrt(<x, x>) (paper
-// Section 2: inner product with a work-group reduction in local memory).
+// reduce.hip -- inner product <x, y>, Euclidean norm sqrt(<x, x>) and sum of
+// magnitudes sum |x_i| (paper Section 2: inner product with a work-group
+// reduction in local memory; the other two read one vector).
 //
 // Stage 1: every thread accumulates its packs (same pack walk, increment
 // schemes and nontemporal 16-byte loads as the streaming kernels) into U independent accumulators in the
@@ -14,7 +15,17 @@
 
 namespace bwla {
 
-template <typename T, int V, int U, bool COMP, bool SQ>
+// One term of the reduction: x_i y_i, x_i^2, or |x_i| (an exact product by 1).
+template <int MODE, bool EXACT, typename C, bool COMP>
+__device__ __forceinline__ void reduce_term(Acc<C, COMP> &acc, C a, C b)
+{
+    if constexpr (MODE == kRedAbs)
+        acc.template add_prod<true>(abs_c(a), C(1));
+    else
+        acc.template add_prod<EXACT>(a, MODE == kRedSq ? a : b);
+}
+
+template <typename T, int V, int U, bool COMP, int MODE>
 __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y, DD *partials,
                                               void *out, int out_f64, int inc)
 {
@@ -42,34 +53,28 @@ __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             vx[u] = load_pack_nt<T, V>(x + (p + u * stride) * V);
-            if constexpr (!SQ)
+            if constexpr (MODE == kRedDot)
                 vy[u] = load_pack_nt<T, V>(y + (p + u * stride) * V);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                C a = widen(vx[u].v[e]);
-                C b = SQ ? a : widen(vy[u].v[e]);
-                acc[u].template add_prod<EXACT>(a, b);
-            }
+            for (int e = 0; e < V; ++e)
+                reduce_term<MODE, EXACT>(acc[u], widen(vx[u].v[e]),
+                                         MODE == kRedDot ? widen(vy[u].v[e]) : C(0));
     }
     for (; p < end; p += stride) {
         Pack<T, V> vx = load_pack_nt<T, V>(x + p * V), vy;
-        if constexpr (!SQ)
+        if constexpr (MODE == kRedDot)
             vy = load_pack_nt<T, V>(y + p * V);
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            C a = widen(vx.v[e]);
-            C b = SQ ? a : widen(vy.v[e]);
-            acc[0].template add_prod<EXACT>(a, b);
-        }
+        for (int e = 0; e < V; ++e)
+            reduce_term<MODE, EXACT>(acc[0], widen(vx.v[e]), MODE == kRedDot ? widen(vy.v[e]) : C(0));
     }
     const int64_t tail = n - npack * V;
     if (blockIdx.x == 0 && threadIdx.x < tail) {
-        C a = widen(x[npack * V + threadIdx.x]);
-        C b = SQ ? a : widen(y[npack * V + threadIdx.x]);
-        acc[0].template add_prod<EXACT>(a, b);
+        const int64_t i = npack * V + threadIdx.x;
+        reduce_term<MODE, EXACT>(acc[0], widen(x[i]), MODE == kRedDot ? widen(y[i]) : C(0));
     }
     DD v = acc[0].to_dd();
 #pragma unroll
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y,
     if (threadIdx.x == 0) {
         if (gridDim.x == 1) {
             double r = bs.hi + bs.lo;
-            store_out(out, 0, out_f64, SQ ? __builtin_sqrt(r) : r);
+            store_out(out, 0, out_f64, MODE == kRedSq ? __builtin_sqrt(r) : r);
         } else {
             partials[blockIdx.x] = bs;
         }
@@ -115,28 +120,34 @@ __global__ __launch_bounds__(256) void k_combine_scalar(const DD *partials, int6
 #endif
 
 template <typename T>
-hipError_t launch_dot(int64_t n, bool comp, bool square, const void *x, const void *y, int out_f64,
+hipError_t launch_dot(int64_t n, bool comp, int mode, const void *x, const void *y, int out_f64,
                       void *out, void *ws, const Cfg &c, hipStream_t s)
 {
     DD *partials = (DD *)ws;
     hipError_t e = with_vec(c.vec, [&](auto V) {
         return with_unroll(c.unroll, [&](auto U) {
             return with_bool(comp, [&](auto CP) {
-                return with_bool(square, [&](auto SQ) {
-                    hipLaunchKernelGGL((k_dot<T, V.value, U.value, CP.value, SQ.value>), dim3(c.grid),
+                auto go = [&](auto M) {
+                    hipLaunchKernelGGL((k_dot<T, V.value, U.value, CP.value, M.value>), dim3(c.grid),
                                        dim3(c.block), 0, s, n, (const T *)x, (const T *)y, partials,
                                        out, out_f64, c.inc);
                     return hipGetLastError();
-                });
+                };
+                switch (mode) {
+                case kRedDot: return go(std::integral_constant<int, kRedDot>{});
+                case kRedSq: return go(std::integral_constant<int, kRedSq>{});
+                case kRedAbs: return go(std::integral_constant<int, kRedAbs>{});
+                default: return hipErrorInvalidValue;
+                }
             });
         });
     });
     if (e != hipSuccess || c.grid == 1)
         return e;
-    return launch_combine_scalar(partials, c.grid, comp, square, out_f64, out, s);
+    return launch_combine_scalar(partials, c.grid, comp, mode == kRedSq, out_f64, out, s);
 }
 
-template hipError_t launch_dot<BWLA_T>(int64_t, bool, bool, const void *, const void *, int, void *,
+template hipError_t launch_dot<BWLA_T>(int64_t, bool, int, const void *, const void *, int, void *,
                                        void *, const Cfg &, hipStream_t);
 
 #if BWLA_T_IS_F64

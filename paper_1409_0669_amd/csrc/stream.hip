@@ -1,6 +1,7 @@
 // stream.hip -- streaming kernels: vector copy x <- y and scaled vector
-// addition x <- alpha y + beta z (paper Section 2), and the fused update of a
-// conjugate-gradient-style step (x += a p, r -= a q, <r, r> in one pass).
+// addition x <- alpha y + beta z (paper Section 2), scaling x <- alpha y (the
+// BLAS scal), and the fused update of a conjugate-gradient-style step
+// (x += a p, r -= a q, <r, r> in one pass).
 //
 // Work decomposition.  The vector is cut into packs of V consecutive elements
 // (the paper's vector data types).  Each thread handles U packs per loop trip,
@@ -64,6 +65,45 @@ __global__ __launch_bounds__(1024) void k_copy(int64_t n, const T *y, T *x, int 
     const int64_t tail = n - npack * V;
     if (blockIdx.x == 0 && threadIdx.x < tail)
         x[npack * V + threadIdx.x] = y[npack * V + threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// scal: x_i = RN_T(a * y_i) (x may be y: the in-place BLAS scal)
+// ---------------------------------------------------------------------------
+template <typename T, int V, int U>
+__global__ __launch_bounds__(1024) void k_scal(int64_t n, compute_t<T> a, const compute_t<T> *adev,
+                                               const T *y, T *x, int inc)
+{
+    if (adev)
+        a = a * *adev;
+    const int64_t npack = n / V;
+    Range rg = pack_range(npack, inc);
+    int64_t p = rg.begin;
+    for (; p + (U - 1) * rg.stride < rg.end; p += U * rg.stride) {
+        Pack<T, V> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = load_pack_nt<T, V>(y + (p + u * rg.stride) * V);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                v[u].v[e] = narrow<T>(a * widen(v[u].v[e]));
+            store_pack_nt<T, V>(x + (p + u * rg.stride) * V, v[u]);
+        }
+    }
+    for (; p < rg.end; p += rg.stride) {
+        Pack<T, V> v = load_pack_nt<T, V>(y + p * V);
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            v.v[e] = narrow<T>(a * widen(v.v[e]));
+        store_pack_nt<T, V>(x + p * V, v);
+    }
+    const int64_t tail = n - npack * V;
+    if (blockIdx.x == 0 && threadIdx.x < tail) {
+        const int64_t i = npack * V + threadIdx.x;
+        x[i] = narrow<T>(a * widen(y[i]));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -213,6 +253,20 @@ hipError_t launch_copy(int64_t n, const void *y, void *x, const Cfg &c, hipStrea
 }
 
 template <typename T>
+hipError_t launch_scal(int64_t n, double alpha, const void *adev, const void *y, void *x, const Cfg &c,
+                       hipStream_t s)
+{
+    using C = compute_t<T>;
+    return with_vec(c.vec, [&](auto V) {
+        return with_unroll(c.unroll, [&](auto U) {
+            hipLaunchKernelGGL((k_scal<T, V.value, U.value>), dim3(c.grid), dim3(c.block), 0, s, n, (C)alpha,
+                               (const C *)adev, (const T *)y, (T *)x, c.inc);
+            return hipGetLastError();
+        });
+    });
+}
+
+template <typename T>
 hipError_t launch_axpby(int64_t n, double alpha, const void *adev, const void *y, double beta,
                         const void *bdev, const void *z, void *x, const Cfg &c, hipStream_t s)
 {
@@ -250,6 +304,8 @@ hipError_t launch_cg(int64_t n, bool comp, double alpha, const void *adev, void 
 }
 
 template hipError_t launch_copy<BWLA_T>(int64_t, const void *, void *, const Cfg &, hipStream_t);
+template hipError_t launch_scal<BWLA_T>(int64_t, double, const void *, const void *, void *, const Cfg &,
+                                        hipStream_t);
 template hipError_t launch_axpby<BWLA_T>(int64_t, double, const void *, const void *, double,
                                          const void *, const void *, void *, const Cfg &, hipStream_t);
 template hipError_t launch_cg<BWLA_T>(int64_t, bool, double, const void *, void *, const void *,

@@ -50,6 +50,17 @@ def _vec(t: torch.Tensor, name: str) -> None:
         raise BwlaError(L.ERR_INVALID_ARG, "%s must be a contiguous 1-D tensor" % name)
 
 
+def _svec(t: torch.Tensor, name: str) -> int:
+    """A 1-D GPU tensor with any positive stride; returns its increment."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise BwlaError(L.ERR_INVALID_ARG, "%s must be a GPU tensor" % name)
+    if t.dim() != 1:
+        raise BwlaError(L.ERR_INVALID_ARG, "%s must be a 1-D tensor" % name)
+    return 1 if t.numel() <= 1 else int(t.stride(0))
+
+
 def _same(dtype, device, *ts) -> None:
     for t in ts:
         if t.dtype != dtype:
@@ -101,14 +112,18 @@ def workspace_size(op: int, dtype: torch.dtype, acc="plain", layout: int = L.ROW
 # operations
 # ---------------------------------------------------------------------------
 def copy(y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    """x <- y."""
-    _vec(y, "y")
-    x = torch.empty_like(y) if out is None else out
-    _vec(x, "out")
+    """x <- y.  Strided 1-D views are accepted (increment = stride)."""
+    incy = _svec(y, "y")
+    x = torch.empty(y.numel(), dtype=y.dtype, device=y.device) if out is None else out
+    incx = _svec(x, "out")
     _same(y.dtype, y.device, x)
     if x.numel() != y.numel():
         raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
-    check(lib.bwla_copy(dtype_code(y.dtype), y.numel(), y.data_ptr(), x.data_ptr(), _stream(y.device)))
+    if incx == 1 and incy == 1:
+        check(lib.bwla_copy(dtype_code(y.dtype), y.numel(), y.data_ptr(), x.data_ptr(), _stream(y.device)))
+    else:
+        check(lib.bwla_copy_strided(dtype_code(y.dtype), y.numel(), y.data_ptr(), incy, x.data_ptr(), incx,
+                                    _stream(y.device)))
     return x
 
 
@@ -117,23 +132,39 @@ def axpby(alpha: float, y: torch.Tensor, beta: float, z: torch.Tensor, out: torc
     """x <- alpha*y + beta*z, computed as RN(fma(a, y, RN(b*z))) in the compute
     precision.  ``out`` may be ``y`` or ``z`` (in-place).  ``alpha_dev`` /
     ``beta_dev``: optional one-element device tensors of the compute dtype that
-    multiply the host factors."""
-    _vec(y, "y")
-    _vec(z, "z")
+    multiply the host factors.  Strided 1-D views are accepted."""
+    incy = _svec(y, "y")
+    incz = _svec(z, "z")
     _same(y.dtype, y.device, z)
-    x = torch.empty_like(y) if out is None else out
-    _vec(x, "out")
+    x = torch.empty(y.numel(), dtype=y.dtype, device=y.device) if out is None else out
+    incx = _svec(x, "out")
     _same(y.dtype, y.device, x)
     if not (x.numel() == y.numel() == z.numel()):
         raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
-    cd = compute_dtype(y.dtype)
-    for name, s in (("alpha_dev", alpha_dev), ("beta_dev", beta_dev)):
-        if s is not None and (s.dtype != cd or s.numel() != 1 or s.device != y.device):
-            raise BwlaError(L.ERR_INVALID_ARG, "%s must be one %s element on %s" % (name, cd, y.device))
-    check(lib.bwla_axpby(dtype_code(y.dtype), y.numel(), float(alpha),
-                         None if alpha_dev is None else alpha_dev.data_ptr(), y.data_ptr(), float(beta),
-                         None if beta_dev is None else beta_dev.data_ptr(), z.data_ptr(), x.data_ptr(),
-                         _stream(y.device)))
+    ad, bd = _dev_scalar(y, alpha_dev, "alpha_dev"), _dev_scalar(y, beta_dev, "beta_dev")
+    if incx == incy == incz == 1:
+        check(lib.bwla_axpby(dtype_code(y.dtype), y.numel(), float(alpha), ad, y.data_ptr(), float(beta), bd,
+                             z.data_ptr(), x.data_ptr(), _stream(y.device)))
+    else:
+        check(lib.bwla_axpby_strided(dtype_code(y.dtype), y.numel(), float(alpha), ad, y.data_ptr(), incy,
+                                     float(beta), bd, z.data_ptr(), incz, x.data_ptr(), incx, _stream(y.device)))
+    return x
+
+
+def _dev_scalar(like: torch.Tensor, s: torch.Tensor | None, name: str):
+    if s is None:
+        return None
+    cd = compute_dtype(like.dtype)
+    if s.dtype != cd or s.numel() != 1 or s.device != like.device:
+        raise BwlaError(L.ERR_INVALID_ARG, "%s must be one %s element on %s" % (name, cd, like.device))
+    return s.data_ptr()
+
+
+def scal(alpha: float, x: torch.Tensor, alpha_dev: torch.Tensor | None = None) -> torch.Tensor:
+    """x <- alpha x in place (x_i = RN(a x_i)); strided 1-D views accepted."""
+    incx = _svec(x, "x")
+    check(lib.bwla_scal(dtype_code(x.dtype), x.numel(), float(alpha), _dev_scalar(x, alpha_dev, "alpha_dev"),
+                        x.data_ptr(), incx, _stream(x.device)))
     return x
 
 
@@ -151,26 +182,37 @@ def _scalar_out(dtype, out_dtype, device, out):
 def dot(x: torch.Tensor, y: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
         out: torch.Tensor | None = None) -> torch.Tensor:
     """<x, y> as a 0-dim device tensor (float64 for f64 input, float32 by
-    default otherwise)."""
-    _vec(x, "x")
-    _vec(y, "y")
+    default otherwise).  Strided 1-D views are accepted."""
+    incx = _svec(x, "x")
+    incy = _svec(y, "y")
     _same(x.dtype, x.device, y)
     if x.numel() != y.numel():
         raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
     out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
     ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
-    check(lib.bwla_dot(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), y.data_ptr(), oc,
-                       out.data_ptr(), ws, wsn, _stream(x.device)))
+    check(lib.bwla_dot_strided(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, y.data_ptr(), incy,
+                               oc, out.data_ptr(), ws, wsn, _stream(x.device)))
     return out
 
 
 def nrm2(x: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
          out: torch.Tensor | None = None) -> torch.Tensor:
-    """sqrt(<x, x>) as a 0-dim device tensor."""
-    _vec(x, "x")
+    """sqrt(<x, x>) as a 0-dim device tensor; strided 1-D views accepted."""
+    incx = _svec(x, "x")
     out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
     ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
-    check(lib.bwla_nrm2(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), oc, out.data_ptr(), ws, wsn,
+    check(lib.bwla_nrm2_strided(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, oc, out.data_ptr(),
+                                ws, wsn, _stream(x.device)))
+    return out
+
+
+def asum(x: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
+         out: torch.Tensor | None = None) -> torch.Tensor:
+    """sum |x_i| as a 0-dim device tensor; strided 1-D views accepted."""
+    incx = _svec(x, "x")
+    out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
+    ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
+    check(lib.bwla_asum(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, oc, out.data_ptr(), ws, wsn,
                         _stream(x.device)))
     return out
 
@@ -189,13 +231,16 @@ def matrix_layout(A: torch.Tensor):
 
 
 def gemv(A: torch.Tensor, x: torch.Tensor, trans: bool = False, acc="plain",
-         out_dtype: torch.dtype | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
-    """y = op(A) x with op(A) = A or A^T.  The layout (row- or column-major,
-    with leading dimension) is read from A's strides."""
+         out_dtype: torch.dtype | None = None, out: torch.Tensor | None = None, alpha: float = 1.0,
+         beta: float = 0.0) -> torch.Tensor:
+    """y = alpha op(A) x + beta y with op(A) = A or A^T (alpha = 1, beta = 0:
+    y = op(A) x, y not read).  The layout (row- or column-major, with leading
+    dimension) is read from A's strides; x and ``out`` may be strided 1-D
+    views.  beta != 0 needs ``out`` (it is read)."""
     if not A.is_cuda:
         raise BwlaError(L.ERR_INVALID_ARG, "A must be a GPU tensor")
     layout, lda = matrix_layout(A)
-    _vec(x, "x")
+    incx = _svec(x, "x")
     _same(A.dtype, A.device, x)
     m, n = A.shape
     out_len, in_len = (n, m) if trans else (m, n)
@@ -204,14 +249,25 @@ def gemv(A: torch.Tensor, x: torch.Tensor, trans: bool = False, acc="plain",
     od = default_out_dtype(A.dtype) if out_dtype is None else out_dtype
     if od not in (torch.float64, torch.float32):
         raise BwlaError(L.ERR_UNSUPPORTED, "output dtype %s" % od)
+    if beta != 0.0 and out is None:
+        raise BwlaError(L.ERR_INVALID_ARG, "beta != 0 needs out (y is read)")
     y = torch.empty(out_len, dtype=od, device=A.device) if out is None else out
-    _vec(y, "out")
+    incy = _svec(y, "out")
     if y.numel() != out_len or y.dtype != od:
         raise BwlaError(L.ERR_INVALID_ARG, "out must have %d %s entries" % (out_len, od))
-    op = L.OP_GEMV_ROWS
-    ws, wsn = _ws_ptr(workspace(workspace_size(op, A.dtype, acc, layout, int(trans), m, n), A.device))
-    check(lib.bwla_gemv(dtype_code(A.dtype), _ACC[acc], layout, int(trans), m, n, A.data_ptr(), lda,
-                        x.data_ptr(), _DTYPE[od], y.data_ptr(), ws, wsn, _stream(A.device)))
+    if alpha == 1.0 and beta == 0.0 and incx == 1 and incy == 1:
+        op = L.OP_GEMV_ROWS
+        ws, wsn = _ws_ptr(workspace(workspace_size(op, A.dtype, acc, layout, int(trans), m, n), A.device))
+        check(lib.bwla_gemv(dtype_code(A.dtype), _ACC[acc], layout, int(trans), m, n, A.data_ptr(), lda,
+                            x.data_ptr(), _DTYPE[od], y.data_ptr(), ws, wsn, _stream(A.device)))
+        return y
+    nbytes = ctypes.c_size_t()
+    check(lib.bwla_gemv_ex_workspace_size(dtype_code(A.dtype), _DTYPE[od], layout, int(trans), m, n,
+                                          ctypes.byref(nbytes)))
+    ws, wsn = _ws_ptr(workspace(nbytes.value, A.device))
+    check(lib.bwla_gemv_ex(dtype_code(A.dtype), _ACC[acc], layout, int(trans), m, n, float(alpha), A.data_ptr(),
+                           lda, x.data_ptr(), incx, float(beta), _DTYPE[od], y.data_ptr(), incy, ws, wsn,
+                           _stream(A.device)))
     return y
 
 

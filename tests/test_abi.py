@@ -236,3 +236,65 @@ def test_gemv_dot_workspace_size(L):
     assert lib.bwla_gemv_dot_workspace_size(0, 0, 0, -1, 5, ctypes.byref(b)) == L.ERR_INVALID_ARG
     assert lib.bwla_gemv_dot_workspace_size(0, 3, 0, 1, 5, ctypes.byref(b)) == L.ERR_INVALID_ARG
     assert lib.bwla_gemv_dot_workspace_size(0, 0, 0, 1, 5, None) == L.ERR_INVALID_ARG
+
+
+def test_strided_validation(L):
+    """Increments: zero output increments, overlaps and oversize strides are
+    caught before anything is enqueued.  Every call here fails validation
+    (none may reach a launch with these placeholder addresses)."""
+    lib = L.lib
+    X, Y, Z = FAKE, FAKE + (1 << 30), FAKE + (2 << 30)
+    assert lib.bwla_copy_strided(0, 10, Y, 1, X, 0, None) == L.ERR_INVALID_ARG        # output inc 0
+    assert lib.bwla_copy_strided(0, -1, Y, 1, X, 1, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_copy_strided(5, 10, Y, 1, X, 2, None) == L.ERR_UNSUPPORTED
+    assert lib.bwla_copy_strided(0, 0, None, 3, None, 2, None) == L.OK               # empty
+    assert lib.bwla_copy_strided(0, 10, None, 2, X, 2, None) == L.ERR_INVALID_ARG
+    # same elements, opposite directions: not an exact alias
+    assert lib.bwla_copy_strided(0, 10, X, -2, X, 2, None) == L.ERR_INVALID_ARG
+    # interleaved f64 vectors 8 bytes apart with stride 2 share no element,
+    # but stride 2 vectors 4 bytes apart do
+    assert lib.bwla_copy_strided(0, 10, X + 4, 2, X, 2, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_copy_strided(0, 1 << 40, X, 1 << 30, Y, 1, None) == L.ERR_INVALID_ARG  # too large
+    assert lib.bwla_axpby_strided(0, 10, 1.0, None, Y, 2, 1.0, None, Z, 3, X, 0, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_axpby_strided(0, 10, 1.0, None, X + 4, 3, 1.0, None, Z, 3, X, 3, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_axpby_strided(0, 10, 1.0, X + 16, Y, 2, 1.0, None, Z, 2, X, 2, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_scal(0, 10, 2.0, None, X, 0, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_scal(0, 10, 2.0, None, None, 1, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_scal(0, 10, 2.0, X + 8, X, 1, None) == L.ERR_INVALID_ARG          # device scalar inside x
+    assert lib.bwla_scal(0, 0, 2.0, None, None, 0, None) == L.OK
+    ws = FAKE + (3 << 30)
+    for fn, args in ((lib.bwla_dot_strided, (X, 2, Y, -3)), ):
+        assert fn(0, 0, 10, *args, 0, X + 8, ws, 1 << 20, None) == L.ERR_INVALID_ARG  # out inside x's span
+        assert fn(0, 0, 10, *args, 1, Z, ws, 1 << 20, None) == L.ERR_UNSUPPORTED      # f32 out of f64 data
+        assert fn(0, 0, 10, *args, 0, None, ws, 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_nrm2_strided(0, 0, 10, X, -2, 0, X + 16, ws, 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_asum(0, 3, 10, X, 1, 0, Z, ws, 1 << 20, None) == L.ERR_UNSUPPORTED  # accumulation mode
+    assert lib.bwla_asum(0, 0, 10, X, 1, 0, X + 40, ws, 1 << 20, None) == L.ERR_INVALID_ARG
+    # a large strided reduction needs its partials
+    assert lib.bwla_asum(0, 0, 1 << 24, X, 2, 0, Z, None, 0, None) == L.ERR_WORKSPACE
+
+
+def test_gemv_ex_validation_and_workspace(L):
+    lib = L.lib
+    A, x, y, ws = FAKE, FAKE + (1 << 30), FAKE + (2 << 30), FAKE + (3 << 30)
+    args = (0, 0, 0, 0, 10, 20, 2.0, A, 20)
+    assert lib.bwla_gemv_ex(*args, x, 2, 1.0, 0, y, 0, ws, 1 << 20, None) == L.ERR_INVALID_ARG    # incy 0
+    assert lib.bwla_gemv_ex(*args, x, 2, 1.0, 1, y, 1, ws, 1 << 20, None) == L.ERR_UNSUPPORTED    # f32 out, f64
+    assert lib.bwla_gemv_ex(*args, x, 2, 1.0, 0, None, 1, ws, 1 << 20, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_gemv_ex(*args, x, 2, 1.0, 0, x + 8, 1, ws, 1 << 20, None) == L.ERR_INVALID_ARG  # y in x
+    assert lib.bwla_gemv_ex(*args, x, 2, 1.0, 0, A + 16, 3, ws, 1 << 20, None) == L.ERR_INVALID_ARG  # y in A
+    assert lib.bwla_gemv_ex(*args, x, 2, 1.0, 0, y, 1, None, 0, None) == L.ERR_WORKSPACE
+    assert lib.bwla_gemv_ex(0, 0, 0, 0, 0, 20, 2.0, A, 20, x, 2, 1.0, 0, None, 1, None, 0, None) == L.OK
+    b, g = ctypes.c_size_t(), ctypes.c_size_t()
+    for t, ot in ((0, 0), (1, 1), (1, 0), (2, 1)):
+        for layout in (0, 1):
+            for trans in (0, 1):
+                for (m, n) in [(1, 1), (37, 3000), (16384, 16384)]:
+                    assert lib.bwla_gemv_ex_workspace_size(t, ot, layout, trans, m, n, ctypes.byref(b)) == L.OK
+                    assert lib.bwla_workspace_size(L.OP_GEMV_ROWS, t, 0, layout, trans, m, n,
+                                                   ctypes.byref(g)) == L.OK
+                    out_len, in_len = (n, m) if trans else (m, n)
+                    es, os_ = (8, 4, 2)[t], (8 if ot == 0 else 4)
+                    assert b.value >= g.value + out_len * os_ + in_len * es
+    assert lib.bwla_gemv_ex_workspace_size(2, 2, 0, 0, 5, 5, ctypes.byref(b)) == L.ERR_UNSUPPORTED
+    assert lib.bwla_gemv_ex_workspace_size(0, 0, 0, 0, 0, 5, ctypes.byref(b)) == L.OK and b.value == 0

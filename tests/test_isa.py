@@ -97,7 +97,7 @@ def test_batched_kernel_draws_work_in_a_uniform_loop(ctype, asm_dir):
     assert found == 4
 
 
-@pytest.mark.parametrize("src", ["stream", "reduce", "gemv", "ger", "batched"])
+@pytest.mark.parametrize("src", ["stream", "reduce", "gemv", "ger", "batched", "strided"])
 def test_no_barrier_in_divergent_loop(src, asm_dir):
     asm = compile_asm(src, "float", asm_dir)
     hazards = [(name, bad) for name, lines in functions(asm) for bad in [divergent_loops_with_barrier(lines)] if bad]
