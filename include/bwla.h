@@ -302,7 +302,7 @@ void bwla_batch_plan_destroy(bwla_batch_plan *p);
 
 /* ---- configuration table ---------------------------------------------------
  * One entry per (op, storage type, size class).  Size class by the bytes the
- * call streams: 0 < 1 MiB, 1 < 16 MiB, 2 < 256 MiB, 3 otherwise; pass -1 to
+ * call streams: 0 < 1 MiB, 1 < 16 MiB, 2 < 256 MiB, 3 < 1 GiB, 4 otherwise; pass -1 to
  * set every class.  cfg == NULL restores the defaults.  The table is shared
  * by all threads (mutex-guarded).  If the environment variable BWLA_TUNING
  * names a tuning table, it is loaded before the first call resolves a

@@ -67,7 +67,7 @@ int device_cus()
 // ---------------------------------------------------------------------------
 // configuration table
 // ---------------------------------------------------------------------------
-constexpr int kClasses = 4;
+constexpr int kClasses = 5;
 std::mutex g_cfg_mu;
 bwla_config g_table[BWLA_OP_COUNT][3][kClasses]; // zero-initialised: all defaults
 
@@ -79,7 +79,9 @@ int size_class(double bytes)
         return 1;
     if (bytes < 268435456.0)
         return 2;
-    return 3;
+    if (bytes < 1073741824.0)
+        return 3;
+    return 4;
 }
 
 bool load_table_file(const char *path, std::string *err);

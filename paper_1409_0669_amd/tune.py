@@ -79,7 +79,9 @@ def size_class(nbytes: float) -> int:
         return 1
     if nbytes < 1 << 28:
         return 2
-    return 3
+    if nbytes < 1 << 30:
+        return 3
+    return 4
 
 
 # ---- timing ----------------------------------------------------------------
@@ -239,7 +241,7 @@ def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
     cus = L.lib.bwla_device_cus()
     ops.reset_config()
     entries, report = [], {"device": torch.cuda.get_device_name(), "cus": cus, "results": [], "copy_proxy": {}}
-    vec_sizes = (1 << 16, 1 << 20, 1 << 23, 1 << 26)
+    vec_sizes = (1 << 16, 1 << 20, 1 << 23, 1 << 25, 1 << 26)
     for dn in dtypes:
         dt = _DT[dn]
         cands = _vector_candidates(dt, cus, quick)
@@ -263,7 +265,7 @@ def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
             for cls, cfg in best_for_class.items():
                 entries.append((Workload_table_op(op), dt, cls, cfg))
         report["copy_proxy"][dn] = copy_proxy(proxy_in)
-        for (m, n) in ((1024, 1024), (4096, 4096), (16384, 16384)):
+        for (m, n) in ((1024, 1024), (4096, 4096), (8192, 8192), (16384, 16384)):
             for layout, cands_g in (("row", _rows_candidates(dt, quick)), ("col", _cols_candidates(dt, quick))):
                 w = Workload("gemv", dt, n=n, m=m, layout=layout)
                 default_ms = time_ms(w.run, reps=10)

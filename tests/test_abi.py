@@ -133,7 +133,7 @@ def test_load_tuning(L, tmp_path):
     p = tmp_path / "t.txt"
     p.write_text("# op dtype class block vec unroll grid inc rows split\n"
                  "1 0 -1 512 2 2 0 0 0 0   # axpby f64\n\n"
-                 "3 1 3 256 4 1 0 0 8 2\n")
+                 "3 1 4 256 4 1 0 0 8 2\n")  # class 4: at least 1 GiB
     assert lib.bwla_load_tuning(str(p).encode()) == L.OK
     got = L.Config()
     lib.bwla_get_config(L.OP_AXPBY, 0, 0, 1 << 20, ctypes.byref(got))

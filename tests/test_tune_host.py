@@ -44,9 +44,24 @@ def test_gfx950_space_is_valid_for_the_library():
 
 
 def test_size_class_agrees_with_library():
+    """The tuner's size classes are the library's: give every class its own
+    block size and read back which one a call of a given size uses."""
+    import ctypes
+    from paper_1409_0669_amd import _lib as L
     from paper_1409_0669_amd import tune
-    assert [tune.size_class(b) for b in (0, (1 << 20) - 1, 1 << 20, (1 << 24) + 5, 1 << 28, 1 << 33)] == \
-        [0, 0, 1, 2, 3, 3]
+    sizes = (0, (1 << 20) - 1, 1 << 20, (1 << 24) + 5, 1 << 28, (1 << 30) - 8, 1 << 30, 1 << 33)
+    assert [tune.size_class(b) for b in sizes] == [0, 0, 1, 2, 3, 3, 4, 4]
+    try:
+        for k in range(5):
+            assert L.lib.bwla_set_config(L.OP_COPY, L.F64, k, ctypes.byref(L.Config(block=64 * (k + 1)))) == L.OK
+        assert L.lib.bwla_set_config(L.OP_COPY, L.F64, 5, ctypes.byref(L.Config(block=64))) == L.ERR_INVALID_ARG
+        c = L.Config()
+        for b in sizes:
+            n = b // 16  # a copy streams 2 * 8 bytes per element
+            assert L.lib.bwla_get_config(L.OP_COPY, L.F64, 0, n, ctypes.byref(c)) == L.OK
+            assert c.block == 64 * (tune.size_class(n * 16) + 1), b
+    finally:
+        L.lib.bwla_set_config(L.OP_COPY, L.F64, -1, None)
 
 
 def test_write_table_roundtrip(tmp_path):
