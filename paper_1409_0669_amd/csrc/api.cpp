@@ -1113,6 +1113,7 @@ struct bwla_batch_plan {
     int device = 0;
     int grid = 0, block = 256, vec = 1;
     int64_t n_items = 0, n_dots = 0;
+    int64_t n_gemv_items = 0; // grouped launch: GEMV items come first
     double bytes = 0;
     BatchItem *d_items = nullptr;
     BatchGemv *d_gemv = nullptr;
@@ -1164,6 +1165,7 @@ hipError_t enqueue_batch(bwla_batch_plan *p, hipStream_t s)
     BatchArgs a;
     a.items = p->d_items;
     a.n_items = p->n_items;
+    a.n_gemv_items = p->n_gemv_items;
     a.gemv = p->d_gemv;
     a.dots = p->d_dots;
     a.partials = p->d_partials;
@@ -1267,12 +1269,24 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         b.lda = q.lda;
         b.x = q.x;
         b.y = q.y;
-        int64_t packs = std::max<int64_t>(1, ceil_div(q.n, p->vec));
+        // grouped launch: x staged in LDS when it fits (rows at any alignment),
+        // else 16-byte packs when A's rows and x allow them, else elements
+        int v_item = p->vec;
+        if (!p->persistent) {
+            if (q.n <= tile_stage_elems((int)es))
+                b.mode = kModeStaged, v_item = nv;
+            else if (q.m > 0 && q.n > 0 && fit_vec(nv, es, {q.A, q.x}, q.lda) == nv)
+                b.mode = kModePacked, v_item = nv;
+            else
+                b.mode = kModeScalar, v_item = 1;
+        } else {
+            b.mode = p->vec == 1 ? kModeScalar : kModePacked;
+        }
+        int64_t packs = std::max<int64_t>(1, ceil_div(q.n, v_item));
         int lanes = 1;
         while (lanes < 64 && lanes < packs)
             lanes <<= 1;
         b.lanes = lanes;
-        b.pad = 0;
         if (q.m == 0)
             continue;
         const int64_t rpi = std::max<int64_t>(1, std::min<int64_t>(q.m, kTileElems / std::max<int64_t>(1, q.n)));
@@ -1297,7 +1311,10 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         b.out = q.out;
         b.slot0 = slots;
         b.chunks = (int32_t)std::max<int64_t>(1, ceil_div(q.n, kChunk));
-        b.pad = 0;
+        if (p->persistent)
+            b.mode = p->vec == 1 ? kModeScalar : kModePacked;
+        else
+            b.mode = q.n > 0 && fit_vec(nv, es, {q.x, q.y}) == nv ? kModePacked : kModeScalar;
         for (int c = 0; c < b.chunks; ++c) {
             Work w{};
             w.it.kind = 1;
@@ -1311,7 +1328,16 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         slots += b.chunks;
         p->bytes += 2.0 * q.n * es + os;
     }
-    std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+    // Largest first.  The grouped launch runs GEMV tiles and dot chunks as two
+    // kernels, so it orders by kind first.
+    if (p->persistent)
+        std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
+    else
+        std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) {
+            return a.it.kind != b.it.kind ? a.it.kind < b.it.kind : a.cost > b.cost;
+        });
+    for (const Work &w : work)
+        p->n_gemv_items += w.it.kind == 0;
     std::vector<BatchItem> items(work.size());
     for (size_t i = 0; i < work.size(); ++i)
         items[i] = work[i].it;

@@ -1,7 +1,8 @@
 // batched.hip -- many uneven row-major GEMVs and dots in one launch.
 //
-// Two designs share the work-item list.  The grouped launch (k_grouped,
-// below the persistent kernel) runs one work-group per item.  The
+// Two designs share the work-item list.  The grouped launch (k_grouped_gemv
+// and k_grouped_dot, below the persistent kernel) runs one work-group per
+// item.  The
 // persistent kernel (k_batched) keeps a grid sized to the machine busy from
 // an atomic work queue; it is launched only on explicit opt-in (see the
 // plan code in api.cpp).
@@ -204,6 +205,90 @@ __device__ __forceinline__ void gemv_tile_block(const BatchGemv &g, int64_t rb, 
     }
 }
 
+// GEMV tile with x staged in LDS, for rows of at most tile_stage_elems()
+// entries.  Rows may start anywhere (lda need not keep them 16-byte
+// aligned): each row is read as a head of h < V elements up to its first
+// 16-byte boundary, then whole 16-byte packs, then a tail of fewer than V
+// elements, and the x entry of every A entry comes from LDS.  x is held
+// interleaved by column residue, xs[(c % V) * P + c / V], so the lanes of a
+// group -- which take consecutive packs -- read consecutive LDS words for each
+// element position of a pack, whatever the row's head.  Loop control is
+// wave-uniform; rows past the tile re-read its last row and are not stored.
+template <typename T, int V, bool COMP>
+__device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb, int64_t re, int out_f64,
+                                                 compute_t<T> *xs)
+{
+    using C = compute_t<T>;
+    constexpr bool EXACT = std::is_same<T, bf16_t>::value;
+    // 8-element packs read 8 LDS words each: two rows in flight keep the
+    // registers (and so the waves per SIMD) in line with the other widths
+    constexpr int RB = V >= 8 ? 2 : kTileRowsInFlight, U = kTilePacksInFlight;
+    const int n = (int)g.n;
+    const int P = (n + V - 1) / V;
+    const T *x = (const T *)g.x;
+    for (int c = threadIdx.x; c < n; c += blockDim.x)
+        xs[(c % V) * P + c / V] = widen(x[c]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int G = g.lanes;
+    const int rpw = 64 / G;
+    const int sub = lane / G, gl = lane - sub * G;
+    const T *A = (const T *)g.A;
+    const int64_t slots = (int64_t)nw * rpw;
+    for (int64_t base = rb + (int64_t)wave * rpw; base < re; base += RB * slots) {
+        const T *row[RB];
+        int h[RB], np[RB];
+        int pmax = 0;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int64_t r = base + j * slots + sub;
+            row[j] = A + (r < re ? r : re - 1) * g.lda;
+            const int mis = (int)(((uintptr_t)row[j] & 15) / sizeof(T)); // elements past a 16-byte boundary
+            const int hj = mis ? V - mis : 0;
+            h[j] = hj < n ? hj : n;
+            np[j] = (n - h[j]) / V;
+            pmax = np[j] > pmax ? np[j] : pmax;
+        }
+        Acc<C, COMP> acc[RB];
+        for (int p = gl; p < pmax; p += U * G) {
+            Pack<T, V> av[RB][U];
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (p + u * G < np[j])
+                        av[j][u] = load_pack_nt<T, V>(row[j] + h[j] + (int64_t)(p + u * G) * V);
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (p + u * G < np[j])
+#pragma unroll
+                        for (int e = 0; e < V; ++e) {
+                            const int c = h[j] + e; // column (h + e) + (p + u G) V
+                            acc[j].template add_prod<EXACT>(widen(av[j][u].v[e]),
+                                                            xs[(c % V) * P + c / V + p + u * G]);
+                        }
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            for (int k = gl; k < h[j]; k += G) // head
+                acc[j].template add_prod<EXACT>(widen(row[j][k]), xs[(k % V) * P + k / V]);
+            for (int k = h[j] + np[j] * V + gl; k < n; k += G) // tail
+                acc[j].template add_prod<EXACT>(widen(row[j][k]), xs[(k % V) * P + k / V]);
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            DD d = acc[j].to_dd();
+            for (int m = G >> 1; m >= 1; m >>= 1)
+                d = combine<COMP>(d, shfl_xor_dd(d, m));
+            const int64_t r = base + j * slots + sub;
+            if (gl == 0 && r < re)
+                store_out(g.y, r, out_f64, d.hi + d.lo);
+        }
+    }
+}
+
 // One dot chunk reduced by a whole work-group: each thread keeps
 // kChunkPacksInFlight packs of both operands in flight per trip, two
 // accumulators, then the work-group tree (block_sum, barriers in
@@ -253,18 +338,38 @@ __device__ __forceinline__ void dot_chunk_block(const BatchArgs &a, const BatchI
     }
 }
 
-template <typename T, int V, bool COMP>
-__global__ __launch_bounds__(512) void k_grouped(BatchArgs a)
+// Two kernels: GEMV items (a.items[0, a.n_gemv_items)) and dot items (the
+// rest), so that each gets the registers of its own code paths.
+template <typename T, bool COMP>
+__global__ __launch_bounds__(512) void k_grouped_gemv(BatchArgs a)
 {
-    __shared__ DD lds[16];
+    using C = compute_t<T>;
+    constexpr int NATIVE = 16 / (int)sizeof(T);
+    __shared__ C xs[kTileStageBytes / sizeof(C)];
     const BatchItem w = a.items[blockIdx.x];
+    const BatchGemv &g = a.gemv[w.prob];
     // the item is the same for every thread of the work-group; readfirstlane
-    // makes the branch visibly uniform (block_sum below holds barriers)
-    const int kind = __builtin_amdgcn_readfirstlane(w.kind);
-    if (kind == 0)
-        gemv_tile_block<T, V, COMP>(a.gemv[w.prob], w.begin, w.end, a.out_f64);
+    // makes the branch visibly uniform (the staged tile holds a barrier)
+    const int mode = __builtin_amdgcn_readfirstlane(g.mode);
+    if (mode == kModeStaged)
+        gemv_tile_staged<T, NATIVE, COMP>(g, w.begin, w.end, a.out_f64, xs);
+    else if (mode == kModePacked)
+        gemv_tile_block<T, NATIVE, COMP>(g, w.begin, w.end, a.out_f64);
     else
-        dot_chunk_block<T, V, COMP>(a, w, lds);
+        gemv_tile_block<T, 1, COMP>(g, w.begin, w.end, a.out_f64);
+}
+
+template <typename T, bool COMP>
+__global__ __launch_bounds__(512) void k_grouped_dot(BatchArgs a)
+{
+    constexpr int NATIVE = 16 / (int)sizeof(T);
+    __shared__ DD lds[16];
+    const BatchItem w = a.items[a.n_gemv_items + blockIdx.x];
+    const int mode = __builtin_amdgcn_readfirstlane(a.dots[w.prob].mode); // block_sum holds barriers
+    if (mode == kModePacked)
+        dot_chunk_block<T, NATIVE, COMP>(a, w, lds);
+    else
+        dot_chunk_block<T, 1, COMP>(a, w, lds);
 }
 
 #if BWLA_T_IS_F64 // type-independent kernels live in the f64 object only
@@ -315,16 +420,16 @@ template hipError_t launch_batched<BWLA_T>(const BatchArgs &, bool, int, int, hi
 template <typename T>
 hipError_t launch_grouped(const BatchArgs &a, bool comp, int block, hipStream_t s)
 {
-    constexpr int NATIVE = 16 / (int)sizeof(T);
-    auto go = [&](auto V) {
-        return with_bool(comp, [&](auto CP) {
-            hipLaunchKernelGGL((k_grouped<T, V.value, CP.value>), dim3((unsigned)a.n_items), dim3(block), 0, s, a);
-            return hipGetLastError();
-        });
-    };
-    if (a.vec == 1)
-        return go(std::integral_constant<int, 1>{});
-    return go(std::integral_constant<int, NATIVE>{});
+    return with_bool(comp, [&](auto CP) {
+        const int64_t nd = a.n_items - a.n_gemv_items;
+        if (a.n_gemv_items > 0)
+            hipLaunchKernelGGL((k_grouped_gemv<T, CP.value>), dim3((unsigned)a.n_gemv_items), dim3(block), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || nd <= 0)
+            return e;
+        hipLaunchKernelGGL((k_grouped_dot<T, CP.value>), dim3((unsigned)nd), dim3(block), 0, s, a);
+        return hipGetLastError();
+    });
 }
 
 template hipError_t launch_grouped<BWLA_T>(const BatchArgs &, bool, int, hipStream_t);

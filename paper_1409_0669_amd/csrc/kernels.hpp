@@ -148,13 +148,24 @@ struct BatchItem {
     int32_t chunk;  // chunk index within the dot
     int32_t pad;
 };
+// How the grouped launch reads one problem (the persistent kernel uses the
+// plan-wide BatchArgs::vec instead).
+enum {
+    kModeStaged = 0, // GEMV with n <= tile_stage_elems(): x staged in LDS, 16-byte packs of A
+    kModePacked = 1, // 16-byte packs of every operand (all of them 16-byte aligned)
+    kModeScalar = 2  // one element per access
+};
+constexpr int kTileStageBytes = 32768; // LDS holding the staged x of a GEMV tile
+// Longest x a staged tile takes, for storage elements of `es` bytes (x is
+// held in the compute precision: 8 bytes for f64, 4 otherwise).
+constexpr int tile_stage_elems(int es) { return kTileStageBytes / (es == 8 ? 8 : 4) - 16 / es; }
 struct BatchGemv {
     const void *A;
     int64_t m, n, lda;
     const void *x;
     void *y;
     int32_t lanes; // lanes per row (power of two, <= 64)
-    int32_t pad;
+    int32_t mode;  // kMode*
 };
 struct BatchDot {
     const void *x, *y;
@@ -162,11 +173,12 @@ struct BatchDot {
     void *out;
     int64_t slot0;  // first partial slot of this dot
     int32_t chunks; // number of chunks
-    int32_t pad;
+    int32_t mode;   // kModePacked or kModeScalar
 };
 struct BatchArgs {
     const BatchItem *items;
     int64_t n_items;
+    int64_t n_gemv_items;   // grouped launch: items[0, n_gemv_items) are GEMV tiles, the rest dot chunks
     const BatchGemv *gemv;
     const BatchDot *dots;
     double *partials;       // 2 doubles per dot chunk

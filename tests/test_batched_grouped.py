@@ -140,3 +140,31 @@ def test_grouped_full_workload_sampled(dtype):
     torch.cuda.synchronize()
     for k, i in enumerate(gi):
         assert bitwise_equal(host(gemvs[i][2]), y0[k])
+
+
+# x longer than the LDS stage of a GEMV tile: rows then use 16-byte packs when
+# A's rows and x are 16-byte aligned (n a multiple of the pack width) and
+# single elements otherwise; the shorter rows are staged at any alignment.
+STAGE = {"f64": 4094, "f32": 8188, "bf16": 8184}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("align", [1, 64])
+@pytest.mark.parametrize("block", [64, 256, 512])
+def test_grouped_every_read_mode(dtype, align, block):
+    """Problem starts aligned to `align` elements: with 1, most rows, x and
+    dot operands are misaligned (staged tiles and element-wise dots); with
+    64, GEMVs longer than the stage take 16-byte packs when n allows."""
+    need_gpu()
+    from paper_1409_0669_amd.batch import BatchPlan
+    cap = STAGE[dtype]
+    Ms = np.array([1, 7, 33, 300, 5, 64, 3, 40])
+    Ns = np.array([1, 3, 17, 1000, cap, cap + 2, cap + 8, 9001])
+    Ds = np.array([0, 1, 9, 1000, 65536, 65537, 200003])
+    gemvs, dots = from_sizes(dtype, Ms, Ns, Ds, seed=3, align=align)
+    for acc in ("plain", "compensated"):
+        plan = BatchPlan(gemvs, dots, acc=acc, block=block)
+        plan.run()
+        torch.cuda.synchronize()
+        check(dtype, gemvs, dots)
+        plan.close()
