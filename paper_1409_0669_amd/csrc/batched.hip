@@ -223,11 +223,24 @@ __device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb,
     // 8-element packs read 8 LDS words each: two rows in flight keep the
     // registers (and so the waves per SIMD) in line with the other widths
     constexpr int RB = V >= 8 ? 2 : kTileRowsInFlight, U = kTilePacksInFlight;
+    constexpr int SU = 8; // x entries in flight per thread while staging
     const int n = (int)g.n;
     const int P = (n + V - 1) / V;
     const T *x = (const T *)g.x;
-    for (int c = threadIdx.x; c < n; c += blockDim.x)
-        xs[(c % V) * P + c / V] = widen(x[c]);
+    for (int c0 = threadIdx.x; c0 < n; c0 += SU * blockDim.x) {
+        C v[SU];
+#pragma unroll
+        for (int k = 0; k < SU; ++k) {
+            const int c = c0 + k * (int)blockDim.x;
+            v[k] = c < n ? widen(x[c]) : C(0);
+        }
+#pragma unroll
+        for (int k = 0; k < SU; ++k) {
+            const int c = c0 + k * (int)blockDim.x;
+            if (c < n)
+                xs[(c % V) * P + c / V] = v[k];
+        }
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int G = g.lanes;
@@ -248,6 +261,18 @@ __device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb,
             h[j] = hj < n ? hj : n;
             np[j] = (n - h[j]) / V;
             pmax = np[j] > pmax ? np[j] : pmax;
+        }
+        // The head (h < V elements before the first 16-byte boundary) and the
+        // tail (< V elements after the last whole pack) of each row: lane gl
+        // takes element gl of each; their loads are issued here, with the
+        // packs, and consumed after the pack loop.  Rows of fewer than V
+        // packs may have G < V lanes: the rest is taken at the end.
+        T hv[RB], tv[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int t0 = h[j] + np[j] * V;
+            hv[j] = gl < h[j] ? row[j][gl] : T(0);
+            tv[j] = t0 + gl < n ? row[j][t0 + gl] : T(0);
         }
         Acc<C, COMP> acc[RB];
         for (int p = gl; p < pmax; p += U * G) {
@@ -272,9 +297,14 @@ __device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb,
         }
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
-            for (int k = gl; k < h[j]; k += G) // head
+            const int t0 = h[j] + np[j] * V;
+            if (gl < h[j])
+                acc[j].template add_prod<EXACT>(widen(hv[j]), xs[(gl % V) * P + gl / V]);
+            if (t0 + gl < n)
+                acc[j].template add_prod<EXACT>(widen(tv[j]), xs[((t0 + gl) % V) * P + (t0 + gl) / V]);
+            for (int k = gl + G; k < h[j]; k += G) // only when G < V
                 acc[j].template add_prod<EXACT>(widen(row[j][k]), xs[(k % V) * P + k / V]);
-            for (int k = h[j] + np[j] * V + gl; k < n; k += G) // tail
+            for (int k = t0 + gl + G; k < n; k += G)
                 acc[j].template add_prod<EXACT>(widen(row[j][k]), xs[(k % V) * P + k / V]);
         }
 #pragma unroll

@@ -36,30 +36,54 @@ def compile_asm(src: str, ctype: str, out_dir) -> str:
     return open(out).read()
 
 
-def functions(asm: str):
-    for m in re.finditer(r"^(_ZN4bwla\S+):", asm, re.M):
+def functions(asm: str, prefix: str = "_ZN4bwla"):
+    for m in re.finditer(r"^(%s\S+):" % prefix, asm, re.M):
         end = asm.find(".Lfunc_end", m.end())
         yield m.group(1), asm[m.end():end].split("\n")
 
 
+def loop_structure(lines):
+    """Blocks and loops from the compiler's block annotations.  Returns
+    (blocks, loops): blocks is a list of (start, end, innermost loop header
+    or None); loops maps a header to the list of its enclosing headers.  A
+    header's label line (and its comment continuation lines) names its
+    parent loops ("Parent Loop BBx Depth=k") and itself ("Loop Header"); any
+    other block of a loop says "in Loop: Header=BBx"."""
+    starts = [i for i, l in enumerate(lines) if re.match(r"^(\.LBB\w+:|; %bb\.\d+:)", l)]
+    blocks, loops = [], {}
+    for b, i in enumerate(starts):
+        end = starts[b + 1] if b + 1 < len(starts) else len(lines)
+        note = lines[i]
+        k = i + 1
+        while k < end and re.match(r"^\s+;", lines[k]):
+            note += lines[k]
+            k += 1
+        m = re.match(r"^\.L(BB\w+):", lines[i])
+        if "Loop Header" in note and m:
+            loops[m.group(1)] = re.findall(r"Parent Loop (BB\w+)", note)
+            blocks.append((i, end, m.group(1)))
+        else:
+            h = re.search(r"in Loop: Header=(BB\w+)", note)
+            blocks.append((i, end, h.group(1) if h else None))
+    return blocks, loops
+
+
 def divergent_loops_with_barrier(lines):
-    """Loop headers whose loop is exec-masked (a latch that clears lanes from
-    exec just before looping) and whose header-to-latch range holds s_barrier."""
+    """Headers of exec-masked loops (lanes leave the loop one by one: the
+    loop's own blocks clear exiting lanes with s_andn2_b64 exec, exec, ...)
+    that hold an s_barrier, directly or in a loop nested inside them."""
+    blocks, loops = loop_structure(lines)
+    masked = set()
+    for start, end, h in blocks:
+        if h and any("s_andn2_b64 exec, exec" in l for l in lines[start:end]):
+            masked.add(h)
     bad = []
-    for h, l in enumerate(lines):
-        m = re.match(r"^(\.LBB\w+):.*Loop Header", l)
-        if not m:
+    for start, end, h in blocks:
+        if h is None or not any("s_barrier" in l for l in lines[start:end]):
             continue
-        lab = m.group(1)
-        latches = [k for k, x in enumerate(lines) if k > h and re.search(r"s_c?branch\w*\s+%s\b" % re.escape(lab), x)]
-        pre = range(max(0, h - 4), h)
-        masked = any("s_andn2_b64 exec, exec" in lines[q] for q in pre) or any(
-            "s_andn2_b64 exec, exec" in lines[q] for k in latches for q in range(max(0, k - 4), k))
-        body = lines[h:max(latches)] if latches else lines[h:h + 400]
-        if any("s_andn2_b64 exec, exec" in lines[q] for q in pre):
-            body = body + lines[max(0, h - 60):h]
-        if masked and any("s_barrier" in b for b in body):
-            bad.append(lab)
+        for enclosing in [h] + loops.get(h, []):
+            if enclosing in masked and enclosing not in bad:
+                bad.append(enclosing)
     return bad
 
 
@@ -95,6 +119,20 @@ def test_batched_kernel_draws_work_in_a_uniform_loop(ctype, asm_dir):
             assert not any("s_andn2_b64 exec, exec" in lines[q] for q in range(max(0, k - 4), k)), name
         assert not any("s_andn2_b64 exec, exec" in lines[q] for q in range(max(0, h - 4), h)), name
     assert found == 4
+
+
+def test_detector_on_fixture(asm_dir):
+    """The checker flags a barrier inside a lane-dependent loop and passes
+    one placed after such a loop (host-compiled fixture, never launched)."""
+    out = os.path.join(str(asm_dir), "fixture.s")
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-O3", "--offload-device-only", "-S",
+                    os.path.join(ROOT, "tests", "isa_fixtures", "barrier_loop.hip"), "-o", out],
+                   check=True, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    found = dict((name, divergent_loops_with_barrier(lines)) for name, lines in functions(open(out).read(), "_Z"))
+    bad = [v for k, v in found.items() if "barrier_in_lane_dependent_loop" in k]
+    good = [v for k, v in found.items() if "barrier_after_lane_dependent_loop" in k]
+    assert len(bad) == 1 and bad[0], found
+    assert len(good) == 1 and not good[0], found
 
 
 @pytest.mark.parametrize("src", ["stream", "reduce", "gemv", "ger", "batched", "strided"])
