@@ -1269,20 +1269,23 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         b.lda = q.lda;
         b.x = q.x;
         b.y = q.y;
-        // grouped launch: x staged in LDS when it fits (rows at any alignment),
-        // else 16-byte packs when A's rows and x allow them, else elements
+        // grouped launch: 16-byte packs of every operand when A's rows and x
+        // are 16-byte aligned (x held in registers), else x staged in LDS
+        // when it fits (rows at any alignment), else one element per access
         int v_item = p->vec;
         if (!p->persistent) {
-            if (q.n <= tile_stage_elems((int)es))
-                b.mode = kModeStaged, v_item = nv;
-            else if (q.m > 0 && q.n > 0 && fit_vec(nv, es, {q.A, q.x}, q.lda) == nv)
+            if (q.m > 0 && q.n > 0 && fit_vec(nv, es, {q.A, q.x}, q.lda) == nv)
                 b.mode = kModePacked, v_item = nv;
+            else if (q.n <= tile_stage_elems((int)es))
+                b.mode = kModeStaged, v_item = nv;
             else
                 b.mode = kModeScalar, v_item = 1;
         } else {
             b.mode = p->vec == 1 ? kModeScalar : kModePacked;
         }
         int64_t packs = std::max<int64_t>(1, ceil_div(q.n, v_item));
+        if (b.mode == kModeStaged && !p->persistent) // each lane owns up to kStagedPacks packs of its row
+            packs = ceil_div(packs, kStagedPacks);
         int lanes = 1;
         while (lanes < 64 && lanes < packs)
             lanes <<= 1;

@@ -212,7 +212,12 @@ __device__ __forceinline__ void gemv_tile_block(const BatchGemv &g, int64_t rb, 
 // elements, and the x entry of every A entry comes from LDS.  x is held
 // interleaved by column residue, xs[(c % V) * P + c / V], so the lanes of a
 // group -- which take consecutive packs -- read consecutive LDS words for each
-// element position of a pack, whatever the row's head.  Loop control is
+// element position of a pack, whatever the row's head.
+//
+// A row belongs to a group of G lanes, G sized on the host so that each lane
+// owns about kStagedPacks packs of it: one trip issues all of them (the
+// row's head and tail elements too) before any arithmetic, and two
+// accumulators per lane split the dependency chain.  Loop control is
 // wave-uniform; rows past the tile re-read its last row and are not stored.
 template <typename T, int V, bool COMP>
 __device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb, int64_t re, int out_f64,
@@ -220,9 +225,10 @@ __device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb,
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
-    // 8-element packs read 8 LDS words each: two rows in flight keep the
-    // registers (and so the waves per SIMD) in line with the other widths
-    constexpr int RB = V >= 8 ? 2 : kTileRowsInFlight, U = kTilePacksInFlight;
+    // packs in flight: all of a lane's packs for 2-element packs, half of
+    // them for 4- and 8-element packs (whose x values per trip would not fit
+    // the registers)
+    constexpr int U = V >= 4 ? kStagedPacks / 2 : kStagedPacks;
     constexpr int SU = 8; // x entries in flight per thread while staging
     const int n = (int)g.n;
     const int P = (n + V - 1) / V;
@@ -248,74 +254,54 @@ __device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb,
     const int sub = lane / G, gl = lane - sub * G;
     const T *A = (const T *)g.A;
     const int64_t slots = (int64_t)nw * rpw;
-    for (int64_t base = rb + (int64_t)wave * rpw; base < re; base += RB * slots) {
-        const T *row[RB];
-        int h[RB], np[RB];
-        int pmax = 0;
+    for (int64_t base = rb + (int64_t)wave * rpw; base < re; base += slots) {
+        const int64_t r = base + sub;
+        const T *row = A + (r < re ? r : re - 1) * g.lda;
+        const int mis = (int)(((uintptr_t)row & 15) / sizeof(T)); // elements past a 16-byte boundary
+        const int h = mis ? (V - mis < n ? V - mis : n) : 0;
+        const int np = (n - h) / V;
+        const int t0 = h + np * V;
+        // head (h < V elements before the first 16-byte boundary) and tail
+        // (< V elements after the last whole pack): lane gl takes element gl
+        // of each; rows with G < V lanes finish them after the packs
+        const T hv = gl < h ? row[gl] : T(0);
+        const T tv = t0 + gl < n ? row[t0 + gl] : T(0);
+        int xo[V]; // LDS position of element e of pack q: xs[xo[e] + q]
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
-            const int64_t r = base + j * slots + sub;
-            row[j] = A + (r < re ? r : re - 1) * g.lda;
-            const int mis = (int)(((uintptr_t)row[j] & 15) / sizeof(T)); // elements past a 16-byte boundary
-            const int hj = mis ? V - mis : 0;
-            h[j] = hj < n ? hj : n;
-            np[j] = (n - h[j]) / V;
-            pmax = np[j] > pmax ? np[j] : pmax;
+        for (int e = 0; e < V; ++e)
+            xo[e] = ((h + e) % V) * P + (h + e) / V;
+        Acc<C, COMP> acc[2];
+        int p = gl;
+        for (; p + (U - 1) * G < np; p += U * G) {
+            Pack<T, V> av[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                av[u] = load_pack_nt<T, V>(row + h + (int64_t)(p + u * G) * V);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    acc[u & 1].template add_prod<EXACT>(widen(av[u].v[e]), xs[xo[e] + p + u * G]);
         }
-        // The head (h < V elements before the first 16-byte boundary) and the
-        // tail (< V elements after the last whole pack) of each row: lane gl
-        // takes element gl of each; their loads are issued here, with the
-        // packs, and consumed after the pack loop.  Rows of fewer than V
-        // packs may have G < V lanes: the rest is taken at the end.
-        T hv[RB], tv[RB];
+        for (; p < np; p += G) {
+            const Pack<T, V> a = load_pack_nt<T, V>(row + h + (int64_t)p * V);
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
-            const int t0 = h[j] + np[j] * V;
-            hv[j] = gl < h[j] ? row[j][gl] : T(0);
-            tv[j] = t0 + gl < n ? row[j][t0 + gl] : T(0);
+            for (int e = 0; e < V; ++e)
+                acc[0].template add_prod<EXACT>(widen(a.v[e]), xs[xo[e] + p]);
         }
-        Acc<C, COMP> acc[RB];
-        for (int p = gl; p < pmax; p += U * G) {
-            Pack<T, V> av[RB][U];
-#pragma unroll
-            for (int j = 0; j < RB; ++j)
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (p + u * G < np[j])
-                        av[j][u] = load_pack_nt<T, V>(row[j] + h[j] + (int64_t)(p + u * G) * V);
-#pragma unroll
-            for (int j = 0; j < RB; ++j)
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (p + u * G < np[j])
-#pragma unroll
-                        for (int e = 0; e < V; ++e) {
-                            const int c = h[j] + e; // column (h + e) + (p + u G) V
-                            acc[j].template add_prod<EXACT>(widen(av[j][u].v[e]),
-                                                            xs[(c % V) * P + c / V + p + u * G]);
-                        }
-        }
-#pragma unroll
-        for (int j = 0; j < RB; ++j) {
-            const int t0 = h[j] + np[j] * V;
-            if (gl < h[j])
-                acc[j].template add_prod<EXACT>(widen(hv[j]), xs[(gl % V) * P + gl / V]);
-            if (t0 + gl < n)
-                acc[j].template add_prod<EXACT>(widen(tv[j]), xs[((t0 + gl) % V) * P + (t0 + gl) / V]);
-            for (int k = gl + G; k < h[j]; k += G) // only when G < V
-                acc[j].template add_prod<EXACT>(widen(row[j][k]), xs[(k % V) * P + k / V]);
-            for (int k = t0 + gl + G; k < n; k += G)
-                acc[j].template add_prod<EXACT>(widen(row[j][k]), xs[(k % V) * P + k / V]);
-        }
-#pragma unroll
-        for (int j = 0; j < RB; ++j) {
-            DD d = acc[j].to_dd();
-            for (int m = G >> 1; m >= 1; m >>= 1)
-                d = combine<COMP>(d, shfl_xor_dd(d, m));
-            const int64_t r = base + j * slots + sub;
-            if (gl == 0 && r < re)
-                store_out(g.y, r, out_f64, d.hi + d.lo);
-        }
+        if (gl < h)
+            acc[1].template add_prod<EXACT>(widen(hv), xs[(gl % V) * P + gl / V]);
+        if (t0 + gl < n)
+            acc[1].template add_prod<EXACT>(widen(tv), xs[((t0 + gl) % V) * P + (t0 + gl) / V]);
+        for (int k = gl + G; k < h; k += G) // only when G < V
+            acc[1].template add_prod<EXACT>(widen(row[k]), xs[(k % V) * P + k / V]);
+        for (int k = t0 + gl + G; k < n; k += G)
+            acc[1].template add_prod<EXACT>(widen(row[k]), xs[(k % V) * P + k / V]);
+        DD d = combine<COMP>(acc[0].to_dd(), acc[1].to_dd());
+        for (int m = G >> 1; m >= 1; m >>= 1)
+            d = combine<COMP>(d, shfl_xor_dd(d, m));
+        if (gl == 0 && r < re)
+            store_out(g.y, r, out_f64, d.hi + d.lo);
     }
 }
 

@@ -156,6 +156,7 @@ enum {
     kModeScalar = 2  // one element per access
 };
 constexpr int kTileStageBytes = 32768; // LDS holding the staged x of a GEMV tile
+constexpr int kStagedPacks = 8;        // packs of a row each lane of a staged tile owns (and keeps in flight)
 // Longest x a staged tile takes, for storage elements of `es` bytes (x is
 // held in the compute precision: 8 bytes for f64, 4 otherwise).
 constexpr int tile_stage_elems(int es) { return kTileStageBytes / (es == 8 ? 8 : 4) - 16 / es; }
