@@ -1269,15 +1269,16 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         b.lda = q.lda;
         b.x = q.x;
         b.y = q.y;
-        // grouped launch: 16-byte packs of every operand when A's rows and x
-        // are 16-byte aligned (x held in registers), else x staged in LDS
-        // when it fits (rows at any alignment), else one element per access
+        // grouped launch: x staged in LDS when it fits (rows at any
+        // alignment; measured as fast as, or faster than, x in registers on
+        // aligned rows), else 16-byte packs of every operand when A's rows
+        // and x are 16-byte aligned, else one element per access
         int v_item = p->vec;
         if (!p->persistent) {
-            if (q.m > 0 && q.n > 0 && fit_vec(nv, es, {q.A, q.x}, q.lda) == nv)
-                b.mode = kModePacked, v_item = nv;
-            else if (q.n <= tile_stage_elems((int)es))
+            if (q.n <= tile_stage_elems((int)es))
                 b.mode = kModeStaged, v_item = nv;
+            else if (q.m > 0 && q.n > 0 && fit_vec(nv, es, {q.A, q.x}, q.lda) == nv)
+                b.mode = kModePacked, v_item = nv;
             else
                 b.mode = kModeScalar, v_item = 1;
         } else {
