@@ -188,7 +188,7 @@ Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
     Cfg c;
     c.block = u.block ? u.block : 1024;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A, v}, ld);
-    c.unroll = 1;
+    c.unroll = u.unroll == 2 ? 2 : 1; // packs of each line in flight per thread: 1 or 2
     c.grid = 0;
     c.inc = 0;
     c.rows = u.rows ? u.rows : 2;

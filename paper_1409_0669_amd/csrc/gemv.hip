@@ -11,7 +11,7 @@
 //   (and, with split > 1, one of `split` slices of their length).  Each
 //   thread loads a pack of v once into registers and reuses it for the R
 //   lines, so v is read from cache once per R lines of A; A itself is read
-//   with nontemporal loads (touched once).  The R sums are
+//   with nontemporal loads (touched once), U packs per line in flight.  The R sums are
 //   reduced across the wave (DPP) and across waves through LDS.  With split >
 //   1 each slice writes float64 partials and a second kernel combines them in
 //   slice order.
@@ -45,7 +45,7 @@ template <typename C, bool COMP> __device__ __forceinline__ DD epilogue_term(C w
     return a.to_dd();
 }
 
-template <typename T, int V, int R, bool COMP>
+template <typename T, int V, int R, int U, bool COMP>
 __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const T *A, int64_t ld,
                                                     const T *v, DD *partials, void *out, int out_f64,
                                                     int split, const T *w, DD *dparts)
@@ -67,8 +67,29 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
     const int64_t pb = (int64_t)s * per;
     const int64_t pe = pb + per < kpack ? pb + per : kpack;
 
+    // U trips of the pack loop per iteration, all loads first: R * U packs of
+    // A in flight per thread.  Each row's sum still takes the packs in the
+    // order p, p + blockDim, ..., so U does not change any result.
     Acc<C, COMP> acc[R];
-    for (int64_t p = pb + threadIdx.x; p < pe; p += blockDim.x) {
+    int64_t p = pb + threadIdx.x;
+    for (; p + (int64_t)(U - 1) * blockDim.x < pe; p += (int64_t)U * blockDim.x) {
+        Pack<T, V> xv[U], av[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xv[u] = load_pack<T, V>(v + (p + (int64_t)u * blockDim.x) * V);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                av[u][r] = load_pack_nt<T, V>(row[r] + (p + (int64_t)u * blockDim.x) * V);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    acc[r].template add_prod<EXACT>(widen(av[u][r].v[e]), widen(xv[u].v[e]));
+    }
+    for (; p < pe; p += blockDim.x) {
         Pack<T, V> xv = load_pack<T, V>(v + p * V);
         Pack<T, V> av[R];
 #pragma unroll
@@ -292,12 +313,17 @@ hipError_t launch_gemv_rows(int64_t L, int64_t K, bool comp, const void *A, int6
     hipError_t e = with_vec(c.vec, [&](auto V) {
         return with_rows(c.rows, [&](auto R) {
             return with_bool(comp, [&](auto CP) {
-                const int64_t groups = (L + R.value - 1) / R.value;
-                hipLaunchKernelGGL((k_gemv_rows<T, V.value, R.value, CP.value>),
-                                   dim3((unsigned)(groups * c.split)), dim3(c.block), 0, s, L, K,
-                                   (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split,
-                                   (const T *)w, dparts);
-                return hipGetLastError();
+                auto go = [&](auto U) {
+                    const int64_t groups = (L + R.value - 1) / R.value;
+                    hipLaunchKernelGGL((k_gemv_rows<T, V.value, R.value, U.value, CP.value>),
+                                       dim3((unsigned)(groups * c.split)), dim3(c.block), 0, s, L, K,
+                                       (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split,
+                                       (const T *)w, dparts);
+                    return hipGetLastError();
+                };
+                if (c.unroll == 2)
+                    return go(std::integral_constant<int, 2>{});
+                return go(std::integral_constant<int, 1>{});
             });
         });
     });

@@ -62,8 +62,8 @@ def vector_space(cus: int):
 
 
 def rows_space():
-    return [dict(block=b, vec=v, rows=r, split=s)
-            for b, v, r, s in itertools.product((64, 128, 256, 512, 1024), VECS, ROWS, SPLITS)]
+    return [dict(block=b, vec=v, rows=r, unroll=u, split=s)
+            for b, v, r, u, s in itertools.product((64, 128, 256, 512, 1024), VECS, ROWS, (1, 2), SPLITS)]
 
 
 def cols_space():
@@ -218,8 +218,8 @@ def _vector_candidates(dtype, cus, quick):
 def _rows_candidates(dtype, quick):
     native = 16 // torch.tensor([], dtype=dtype).element_size()
     vecs = (native,) if quick else (max(1, native // 2), native)
-    return [dict(block=b, vec=v, rows=r, split=s) for b in (256, 512, 1024) for v in vecs
-            for r in (1, 2, 4, 8) for s in (0, 1, 2, 4)]
+    return [dict(block=b, vec=v, rows=r, unroll=u, split=s) for b in (256, 512, 1024) for v in vecs
+            for r in (1, 2, 4, 8) for u in (1, 2) for s in (0, 1, 2, 4)]
 
 
 def _cols_candidates(dtype, quick):

@@ -95,9 +95,9 @@ def test_gemv_empty():
     assert ops.gemv(A, torch.zeros(6, dtype=torch.float32, device="cuda")).numel() == 0
 
 
-ROWS_CFG = [dict(block=64, vec=1, rows=1, split=1), dict(block=128, vec=2, rows=2, split=3),
-            dict(block=256, vec=4, rows=8, split=1), dict(block=1024, vec=16, rows=4, split=2),
-            dict(block=512, vec=8, rows=1, split=7)]
+ROWS_CFG = [dict(block=64, vec=1, rows=1, split=1), dict(block=128, vec=2, rows=2, split=3, unroll=2),
+            dict(block=256, vec=4, rows=8, split=1, unroll=2), dict(block=1024, vec=16, rows=4, split=2),
+            dict(block=512, vec=8, rows=1, split=7, unroll=2)]
 COLS_CFG = [dict(block=64, vec=1, unroll=1, split=1), dict(block=128, vec=2, unroll=2, split=3),
             dict(block=256, vec=4, unroll=4, split=1), dict(block=1024, vec=16, unroll=4, split=2),
             dict(block=512, vec=8, unroll=1, split=9)]
@@ -119,6 +119,23 @@ def test_gemv_configs(dtype, cfg):
                     y = ops.gemv(A, x, trans=bool(trans), acc=acc)
                     ref, scale = _ref(A64, x64, trans)
                     check_vector(host(y), ref, scale, TOL[dtype], "%s %s %s" % (cfg, layout, trans))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+def test_gemv_rows_unroll_keeps_the_order(dtype, acc):
+    """Two packs per line in flight take each line's packs in the same order
+    as one: the results are bitwise the same (with and without a split)."""
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    A, _ = mat(1500, 9001, dtype, 39)
+    x, _ = vec(9001, dtype, 40)
+    for split in (1, 3):
+        got = []
+        for u in (1, 2):
+            ops.set_config(L.OP_GEMV_ROWS, DT[dtype], -1, block=256, rows=2, unroll=u, split=split)
+            got.append(host(ops.gemv(A, x, acc=acc)))
+        assert bitwise_equal(got[0], got[1]), split
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
