@@ -1,6 +1,7 @@
 """The library's calls can be captured in a HIP graph (torch.cuda.CUDAGraph):
 they allocate nothing on the device and issue no memset or host
-synchronisation.  A captured sequence of every operation is replayed several
+synchronisation.  A captured sequence of every operation (strided, alpha/beta
+and fused variants included) is replayed several
 times, with eager work and synchronisations between replays, and every replay
 must equal the eager results bitwise (all kernels are deterministic)."""
 from __future__ import annotations
@@ -33,8 +34,16 @@ def _build(dtype):
         "gr": torch.empty(700, dtype=od, device="cuda"), "gc": torch.empty(700, dtype=od, device="cuda"),
         "gt": torch.empty(900, dtype=od, device="cuda"), "gct": torch.empty(900, dtype=od, device="cuda"),
         "ger": torch.empty_like(A), "cg": torch.empty((), dtype=od, device="cuda"),
+        "asum": torch.empty((), dtype=od, device="cuda"), "asum_s": torch.empty((), dtype=od, device="cuda"),
+        "dot_s": torch.empty((), dtype=od, device="cuda"), "copy_s": torch.empty((n + 2) // 3, dtype=y.dtype,
+                                                                                device="cuda"),
+        "axpby_s": torch.zeros(2 * n, dtype=y.dtype, device="cuda"),
     }
-    state = {"x": W.device_draw(n, dtype, 0, 8), "r": W.device_draw(n, dtype, 0, 9)}
+    if dtype != "bf16":  # GEMV with the dot epilogue keeps y in the storage type
+        outs["gd_y"] = torch.empty(700, dtype=y.dtype, device="cuda")
+        outs["gd_s"] = torch.empty((), dtype=od, device="cuda")
+    state = {"x": W.device_draw(n, dtype, 0, 8), "r": W.device_draw(n, dtype, 0, 9),
+             "sc": W.device_draw(n, dtype, 0, 10), "yex": W.device_draw(2 * 700, "f64" if dtype == "f64" else "f32", 0, 11)}
     init = {k: v.clone() for k, v in state.items()}
 
     def step():
@@ -50,6 +59,18 @@ def _build(dtype):
         state["x"].copy_(init["x"])
         state["r"].copy_(init["r"])
         ops.cg_update(0.01, state["x"], p, state["r"], q, out=outs["cg"])
+        ops.asum(y, out=outs["asum"])
+        ops.asum(z[::3], acc="compensated", out=outs["asum_s"])
+        ops.dot(y[::2], z[1::2], out=outs["dot_s"])
+        ops.copy(y[::3], out=outs["copy_s"])
+        outs["axpby_s"].zero_()  # a fill kernel: the gaps between the strided entries stay 0
+        ops.axpby(0.5, y, 2.0, z, out=outs["axpby_s"][::2])
+        state["sc"].copy_(init["sc"])
+        ops.scal(-1.5, state["sc"][::2])
+        state["yex"].copy_(init["yex"])
+        ops.gemv(A, xv, out=state["yex"][::2], alpha=0.5, beta=-2.0)
+        if "gd_y" in outs:
+            ops.gemv_dot(A, xv, xt, out=outs["gd_y"], dot_out=outs["gd_s"])
 
     return step, outs, state
 
