@@ -449,7 +449,7 @@ def main():
     dom_bytes = work[dom_idx][1]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     cfg = ops.get_config(L.OP_GEMV_ROWS, torch.float64, DOMINANT[3], DOMINANT[3])
-    kernel = "k_gemv_rows<double, %d, %d, false>" % (cfg["vec"], cfg["rows"])
+    kernel = "k_gemv_rows<double, %d, %d, %d, false>" % (cfg["vec"], cfg["rows"], cfg["unroll"])
     if cfg["split"] > 1:
         kernel += " + k_combine_lines (split %d)" % cfg["split"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
