@@ -61,7 +61,7 @@ def _build(dtype):
         ops.cg_update(0.01, state["x"], p, state["r"], q, out=outs["cg"])
         ops.asum(y, out=outs["asum"])
         ops.asum(z[::3], acc="compensated", out=outs["asum_s"])
-        ops.dot(y[::2], z[1::2], out=outs["dot_s"])
+        ops.dot(y[1::2], z[2::2], out=outs["dot_s"])
         ops.copy(y[::3], out=outs["copy_s"])
         outs["axpby_s"].zero_()  # a fill kernel: the gaps between the strided entries stay 0
         ops.axpby(0.5, y, 2.0, z, out=outs["axpby_s"][::2])
