@@ -127,8 +127,9 @@ def _median_ms(torch, fn, reps):
 def extra_rows(torch, W, ops, reps):
     """The other rows of the hot path, each timed on its own (median of `reps`
     HIP-event intervals on the launch stream), outside the main metric:
-    adjoint kernels at the differentiation shapes, reduced-precision storage
-    with compensated accumulation, and the composite operations."""
+    the copy, adjoint kernels at the differentiation shapes, reduced-precision
+    storage with compensated accumulation, the composite operations and the
+    BLAS-interface additions."""
     from paper_1409_0669_amd import composite
     out = {}
 
@@ -157,8 +158,15 @@ def extra_rows(torch, W, ops, reps):
     rate("adjoint dot backward f32 n=2^24", 4 * nd * 4,
          lambda: (ops.axpby(1.0, yv, 0.0, yv, out=gx, alpha_dev=zb), ops.axpby(1.0, xv, 0.0, xv, out=gy, alpha_dev=zb)))
     del xv, yv, gx, gy
-    # reduced precision: bf16 and f32 storage, float32 accumulation
+    # the copy, the paper's calibration kernel and tuning proxy (x <- y, 2ns bytes)
     n = 1 << 26
+    for dt in ("f64", "f32", "bf16"):
+        s = {"f64": 8, "f32": 4, "bf16": 2}[dt]
+        a = W.device_draw(n, dt, 0, 905)
+        c = torch.empty_like(a)
+        rate("copy %s n=2^26" % dt, 2 * n * s, lambda: ops.copy(a, out=c))
+        del a, c
+    # reduced precision: bf16 and f32 storage, float32 accumulation
     for dt in ("bf16", "f32"):
         s = 2 if dt == "bf16" else 4
         a = W.device_draw(n, dt, 0, 910)
