@@ -46,3 +46,8 @@ def test_bench_one_step_json():
     r = d["roofline"]
     assert r["bound"] == "hbm" and r["peak"] == 8000.0 and 0 < r["frac"] < 1.2
     assert r["algorithmic_bytes"] == (16384 * 16384 + 2 * 16384) * 8
+    c = d["copy_ceiling"]
+    assert c["gbs"] > 0 and 0 < c["dominant_frac"] < 2 and 0 < c["value_frac"] < 2
+    # working sets under the 256 MiB Infinity Cache are labelled, the 2^26 vectors and 16384^2 matrices are not
+    assert "axpby f32 100000" in d["cache_resident"] and "gemv f64 rowx4096" in d["cache_resident"]
+    assert "axpby f64 67108864" not in d["cache_resident"] and "gemv f64 rowx16384" not in d["cache_resident"]
