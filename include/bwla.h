@@ -87,14 +87,16 @@ typedef enum {
  * global work size; Section 1 and Section 2) with the source variant spelled
  * out.  A zero field means "library default".  Which fields an op uses:
  *   COPY, AXPBY, DOT, NRM2, CG: block, vec, unroll, grid, increment
- *   GEMV_ROWS:        block, vec, rows (lines per block), split (blocks along a line)
+ *   GEMV_ROWS:        block, vec, rows (lines per block), unroll (packs of each
+ *                     line in flight: 1 or 2), split (blocks along a line)
  *   GEMV_COLS:        block, vec, unroll (lines in flight), split (blocks across lines)
  *   GER:              block, vec, rows
  * block:  threads per work-group, a multiple of 64 in [64, 1024]
  * vec:    consecutive elements per thread per access: 1, 2, 4, 8 or 16 (the
  *         paper's vector data types); widths above 16 bytes are issued as
  *         several 16-byte loads
- * unroll: independent accesses in flight per thread per iteration: 1, 2 or 4
+ * unroll: independent accesses in flight per thread per iteration: 1, 2, 4,
+ *         or 8 (8 for DOT and NRM2 only; other operations take 4)
  * grid:   number of work-groups (streaming and reductions)
  * rows:   1, 2, 4 or 8
  * split:  >= 1; values above 1 make several work-groups share one output

@@ -124,8 +124,15 @@ hipError_t launch_dot(int64_t n, bool comp, int mode, const void *x, const void 
                       void *out, void *ws, const Cfg &c, hipStream_t s)
 {
     DD *partials = (DD *)ws;
+    // packs in flight per thread: 1, 2, 4, or 8 (a single stream -- nrm2,
+    // asum -- needs more bytes in flight per thread than two)
+    auto with_unroll_red = [](int u, auto &&f) -> hipError_t {
+        if (u == 8)
+            return f(std::integral_constant<int, 8>{});
+        return with_unroll(u, f);
+    };
     hipError_t e = with_vec(c.vec, [&](auto V) {
-        return with_unroll(c.unroll, [&](auto U) {
+        return with_unroll_red(c.unroll, [&](auto U) {
             return with_bool(comp, [&](auto CP) {
                 auto go = [&](auto M) {
                     hipLaunchKernelGGL((k_dot<T, V.value, U.value, CP.value, M.value>), dim3(c.grid),

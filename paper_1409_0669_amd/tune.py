@@ -207,12 +207,16 @@ DEFAULT_TABLE = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "tun
 _DT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 
 
-def _vector_candidates(dtype, cus, quick):
+def _vector_candidates(dtype, cus, quick, reduction=False):
+    """Streaming candidates; reductions also try eight packs in flight and
+    eight work-groups per CU (more bytes in flight for a single stream)."""
     native = 16 // torch.tensor([], dtype=dtype).element_size()
     vecs = (native,) if quick else (max(1, native // 2), native, min(16, 2 * native))
     blocks = (256, 1024) if quick else (128, 256, 512, 1024)
+    unrolls = (1, 2, 4, 8) if reduction else (1, 2, 4)
+    grids = (1, 2, 4, 8, 0) if reduction else (1, 2, 4, 0)
     return [dict(block=b, vec=v, unroll=u, increment=i, grid=g * cus)
-            for b in blocks for v in vecs for u in (1, 2, 4) for i in (0, 1) for g in (1, 2, 4, 0)]
+            for b in blocks for v in vecs for u in unrolls for i in (0, 1) for g in grids]
 
 
 def _rows_candidates(dtype, quick):
@@ -245,13 +249,14 @@ def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
     for dn in dtypes:
         dt = _DT[dn]
         cands = _vector_candidates(dt, cus, quick)
+        cands_red = _vector_candidates(dt, cus, quick, reduction=True)
         proxy_in = {}
         for op in ("copy", "axpby", "dot", "nrm2", "cg"):
             best_for_class = {}
             for n in vec_sizes:
                 w = Workload(op, dt, n=n)
                 default_ms = time_ms(w.run, reps=10)
-                res = sweep(w, cands, reps=6)
+                res = sweep(w, cands_red if op in ("dot", "nrm2") else cands, reps=6)
                 best = res[0]
                 best_for_class[w.cls] = best[0]  # larger sizes overwrite smaller ones in the same class
                 report["results"].append({"op": op, "dtype": dn, "n": n, "class": w.cls, "bytes": w.bytes,

@@ -126,6 +126,15 @@ def test_config_table(L):
     bad = L.Config(vec=3)
     assert lib.bwla_set_config(L.OP_COPY, 0, 0, ctypes.byref(bad)) == L.ERR_INVALID_ARG
     assert lib.bwla_set_config(99, 0, 0, None) == L.ERR_INVALID_ARG
+    # eight packs in flight: kept for the reductions, four for everything else
+    eight = L.Config(unroll=8)
+    for op, want in ((L.OP_DOT, 8), (L.OP_NRM2, 8), (L.OP_COPY, 4), (L.OP_AXPBY, 4), (L.OP_CG, 4),
+                     (L.OP_GEMV_COLS, 4), (L.OP_GEMV_ROWS, 1)):
+        assert lib.bwla_set_config(op, 0, -1, ctypes.byref(eight)) == L.OK
+        assert lib.bwla_get_config(op, 0, 1024, 1 << 20, ctypes.byref(got)) == L.OK
+        assert got.unroll == want, (op, got.unroll)
+        assert lib.bwla_set_config(op, 0, -1, None) == L.OK
+    assert lib.bwla_set_config(L.OP_DOT, 0, -1, ctypes.byref(L.Config(unroll=3))) == L.ERR_INVALID_ARG
 
 
 def test_load_tuning(L, tmp_path):

@@ -86,6 +86,8 @@ CONFIGS = [
     dict(block=256, vec=4, unroll=4, grid=37),
     dict(block=1024, vec=8, unroll=1, grid=0, increment=1),
     dict(block=512, vec=16, unroll=2, grid=300),
+    dict(block=256, vec=4, unroll=8, grid=2048),
+    dict(block=1024, vec=2, unroll=8, grid=0, increment=1),
 ]
 
 
@@ -96,12 +98,14 @@ def test_dot_configs(dtype, acc, cfg):
     from paper_1409_0669_amd import _lib as L
     from paper_1409_0669_amd import ops
     ops.set_config(L.OP_DOT, DT[dtype], -1, **CONFIGS[cfg])
+    ops.set_config(L.OP_NRM2, DT[dtype], -1, **CONFIGS[cfg])
     for n in (3, 4099, 300017):
         x, x64 = vec(n, dtype, 13)
         y, y64 = vec(n, dtype, 14)
         got = float(ops.dot(x, y, acc=acc).item())
         check_scalar(got, oracle.dot(x64, y64), float(np.abs(x64 * y64).sum()), TOL[dtype], str(CONFIGS[cfg]))
         check_scalar(float(ops.nrm2(x, acc=acc).item()), oracle.nrm2(x64), 0.0, TOL[dtype], "nrm2")
+        check_scalar(float(ops.asum(x, acc=acc).item()), oracle.asum(x64), 0.0, TOL[dtype], "asum")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
