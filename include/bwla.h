@@ -96,7 +96,9 @@ typedef enum {
  *         paper's vector data types); widths above 16 bytes are issued as
  *         several 16-byte loads
  * unroll: independent accesses in flight per thread per iteration: 1, 2, 4,
- *         or 8 (8 for DOT and NRM2 only; other operations take 4)
+ *         or 8 (8 for DOT, NRM2 and GEMV_COLS; the streaming operations take 4)
+ * GEMV_ROWS work-groups are never larger than the packs of one slice of a
+ * line (rounded up to 64 threads), whatever the table says.
  * grid:   number of work-groups (streaming and reductions)
  * rows:   1, 2, 4 or 8
  * split:  >= 1; values above 1 make several work-groups share one output

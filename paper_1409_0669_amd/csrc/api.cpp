@@ -162,7 +162,7 @@ Cfg resolve_vector(int op, int t, int64_t n, std::initializer_list<const void *>
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), ptrs);
     c.unroll = u.unroll ? u.unroll : (op == BWLA_OP_DOT || op == BWLA_OP_NRM2 ? 4 : 1);
     if (c.unroll > 4 && op != BWLA_OP_DOT && op != BWLA_OP_NRM2)
-        c.unroll = 4; // eight packs in flight exist for the reductions only
+        c.unroll = 4; // eight packs in flight exist for the reductions (and the cols GEMV) only
     c.inc = u.increment;
     c.rows = 1;
     c.split = 1;
@@ -207,6 +207,11 @@ Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
     split = std::max<int64_t>(1, std::min<int64_t>(split, std::max<int64_t>(1, K)));
     split = std::min<int64_t>(split, (int64_t)(0x7fffffff / std::max<int64_t>(1, groups)));
     c.split = (int)split;
+    // No more threads than the packs of a slice: a table entry tuned on long
+    // lines would leave most of a work-group idle on short ones.
+    const int64_t per_slice = ceil_div(std::max<int64_t>(1, K / c.vec), split);
+    const int64_t need = std::max<int64_t>(64, ceil_div(per_slice, 64) * 64);
+    c.block = (int)std::min<int64_t>(c.block, need);
     return c;
 }
 
@@ -216,7 +221,7 @@ Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
     Cfg c;
     c.block = u.block ? u.block : 512;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A}, ld);
-    c.unroll = u.unroll ? (u.unroll > 4 ? 4 : u.unroll) : 4;
+    c.unroll = u.unroll ? u.unroll : 4; // lines in flight per wave: 1, 2, 4 or 8
     c.grid = 0;
     c.inc = 0;
     c.rows = 1;

@@ -342,8 +342,14 @@ hipError_t launch_gemv_cols(int64_t L, int64_t K, bool comp, const void *A, int6
 {
     DD *partials = (DD *)ws;
     DD *dparts = w ? (DD *)((char *)ws + dparts_offset) : nullptr;
+    // lines in flight per wave: 1, 2, 4 or 8
+    auto with_unroll_cols = [](int u, auto &&f) -> hipError_t {
+        if (u == 8)
+            return f(std::integral_constant<int, 8>{});
+        return with_unroll(u, f);
+    };
     hipError_t e = with_vec(c.vec, [&](auto V) {
-        return with_unroll(c.unroll, [&](auto U) {
+        return with_unroll_cols(c.unroll, [&](auto U) {
             return with_bool(comp, [&](auto CP) {
                 const int64_t tiles = (K + 64 * V.value - 1) / (64 * V.value);
                 hipLaunchKernelGGL((k_gemv_cols<T, V.value, U.value, CP.value>),

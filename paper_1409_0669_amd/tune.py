@@ -230,7 +230,7 @@ def _cols_candidates(dtype, quick):
     native = 16 // torch.tensor([], dtype=dtype).element_size()
     vecs = (native,) if quick else (max(1, native // 2), native)
     return [dict(block=b, vec=v, unroll=u, split=s) for b in (256, 512, 1024) for v in vecs
-            for u in (2, 4) for s in (0, 1, 2, 4, 8, 16)]
+            for u in (2, 4, 8) for s in (0, 1, 2, 4, 8, 16)]
 
 
 def _ger_candidates(dtype, quick):

@@ -129,7 +129,7 @@ def test_config_table(L):
     # eight packs in flight: kept for the reductions, four for everything else
     eight = L.Config(unroll=8)
     for op, want in ((L.OP_DOT, 8), (L.OP_NRM2, 8), (L.OP_COPY, 4), (L.OP_AXPBY, 4), (L.OP_CG, 4),
-                     (L.OP_GEMV_COLS, 4), (L.OP_GEMV_ROWS, 1)):
+                     (L.OP_GEMV_COLS, 8), (L.OP_GEMV_ROWS, 1)):
         assert lib.bwla_set_config(op, 0, -1, ctypes.byref(eight)) == L.OK
         assert lib.bwla_get_config(op, 0, 1024, 1 << 20, ctypes.byref(got)) == L.OK
         assert got.unroll == want, (op, got.unroll)
@@ -307,3 +307,18 @@ def test_gemv_ex_validation_and_workspace(L):
                     assert b.value >= g.value + out_len * os_ + in_len * es
     assert lib.bwla_gemv_ex_workspace_size(2, 2, 0, 0, 5, 5, ctypes.byref(b)) == L.ERR_UNSUPPORTED
     assert lib.bwla_gemv_ex_workspace_size(0, 0, 0, 0, 0, 5, ctypes.byref(b)) == L.OK and b.value == 0
+
+
+def test_rows_block_fits_the_line(L):
+    """A rows-GEMV work-group never holds more threads than one slice of a
+    line has packs (rounded up to 64), whatever the table says."""
+    lib = L.lib
+    got = L.Config()
+    assert lib.bwla_set_config(L.OP_GEMV_ROWS, 1, -1, ctypes.byref(L.Config(block=1024, vec=4, rows=2, split=1))) == L.OK
+    try:
+        for n, want in ((2048, 512), (16384, 1024), (100, 64), (4096, 1024), (4100, 1024)):
+            assert lib.bwla_get_config(L.OP_GEMV_ROWS, 1, 16384, n, ctypes.byref(got)) == L.OK
+            assert got.block == want, (n, got.block)
+    finally:
+        lib.bwla_set_config(L.OP_GEMV_ROWS, 1, -1, None)
+
