@@ -1,6 +1,6 @@
 """Parity at the full paper-scale sizes, in the launch configuration the
 benchmark times (the shipped tuning table): vectors of 2^26 and 10^7 entries,
-GEMV 4096^2 (every output) and 16384^2 (sampled rows), composite operations at
+GEMV 4096^2 (every output), 16384^2 (sampled rows) and beyond 2^31 elements, composites at
 n = 2^24 and 8192^2 with normal inputs, and the reduced-precision forms."""
 from __future__ import annotations
 
@@ -144,3 +144,25 @@ def test_reduced_precision_compensated_vs_plain(dtype):
     rows = np.sort(np.random.default_rng(3).choice(m, 32, replace=False))
     R64, v64 = host(A[torch.from_numpy(rows).cuda()]), host(v)
     check_vector(yv[rows], oracle.gemv(R64, v64), np.abs(R64) @ np.abs(v64), TOL[dtype], "gemv comp")
+
+
+def test_gemv_beyond_int32_elements():
+    """A 46341 x 46341 float32 matrix has more elements than a 32-bit index
+    holds (2 147 488 281 > 2^31 - 1): y = A x (rows kernel) and y = A^T x
+    (cols kernel on the same bytes) on sampled outputs, including the last
+    row and column, against the oracle on those rows and columns."""
+    from paper_1409_0669_amd import ops
+    m = 46341
+    A = W.device_draw(m * m, "f32", 0, 710).view(m, m)
+    x = W.device_draw(m, "f32", 0, 711)
+    x64 = host(x)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([[0, 1, m // 2, m - 2, m - 1], rng.integers(0, m, 12)]))
+    for acc in ("plain", "compensated"):
+        y = host(ops.gemv(A, x, acc=acc))
+        rows = np.stack([host(A[int(i)]) for i in idx])
+        check_vector(y[idx], oracle.gemv(rows, x64), np.abs(rows) @ np.abs(x64), TOL["f32"], "rows " + acc)
+        yt = host(ops.gemv(A, x, trans=True, acc=acc))
+        cols = np.stack([host(A[:, int(j)].contiguous()) for j in idx])
+        check_vector(yt[idx], oracle.gemv(cols, x64), np.abs(cols) @ np.abs(x64), TOL["f32"], "cols " + acc)
+    del A
