@@ -215,11 +215,8 @@ def _vector_candidates(dtype, cus, quick, reduction=False):
     blocks = (256, 1024) if quick else (128, 256, 512, 1024)
     unrolls = (1, 2, 4, 8) if reduction else (1, 2, 4)
     grids = (1, 2, 4, 8, 0) if reduction else (1, 2, 4, 0)
-    cands = [dict(block=b, vec=v, unroll=u, increment=i, grid=g * cus)
-             for b in blocks for v in vecs for u in unrolls for i in (0, 1) for g in grids]
-    if reduction:  # one work-group: the result is written directly, no second kernel (small vectors)
-        cands += [dict(block=1024, vec=v, unroll=u, increment=0, grid=1) for v in vecs for u in unrolls]
-    return cands
+    return [dict(block=b, vec=v, unroll=u, increment=i, grid=g * cus)
+            for b in blocks for v in vecs for u in unrolls for i in (0, 1) for g in grids]
 
 
 def _rows_candidates(dtype, quick):
