@@ -217,6 +217,7 @@ Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
 
 Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const void *v)
 {
+    (void)v; // x is staged element by element: its alignment does not constrain the pack width
     bwla_config u = lookup(BWLA_OP_GEMV_COLS, t, (double)L * K * dsize(t));
     Cfg c;
     c.block = u.block ? u.block : 512;

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
         for (int wv = 1; wv < nw; ++wv)
             t = combine<COMP>(t, lds[wv * R + threadIdx.x]);
         if (split == 1) {
-            if (threadIdx.x < nr)
+            if ((int)threadIdx.x < nr)
                 store_out(out, l0 + threadIdx.x, out_f64, t.hi + t.lo);
         } else {
             partials[(group * split + s) * R + threadIdx.x] = t;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
     }
     if (w != nullptr && split == 1 && wave == 0) { // the whole first wave
         DD d = {0.0, 0.0};
-        if (threadIdx.x < nr)
+        if ((int)threadIdx.x < nr)
             d = epilogue_term<C, COMP>(widen(w[l0 + threadIdx.x]), (C)(t.hi + t.lo));
         d = wave_sum<COMP>(d);
         if (lane == 0)
