@@ -16,6 +16,13 @@ The report gives:
 * the single-configuration comparison (Table 2): every operation run with the
   copy's best configuration against its own best.
 
+The matrix-vector product is swept over the rows-kernel space
+(``tune.rows_space``: work-group size, vector width, rows per work-group,
+unroll, split) at the paper's 2048 x 2048 and at 16384 x 16384.  Its Table 2
+analogue runs the paper's mapping -- one work-group per row -- with the
+copy's best work-group size and vector width, against the GEMV's own best;
+the best of the one-row-per-work-group configurations is reported as well.
+
 Run on the GPU: ``python -m paper_1409_0669_amd.study --json OUT.json --md OUT.md``.
 """
 from __future__ import annotations
@@ -39,6 +46,43 @@ def _key(c):
     return tuple(sorted(c.items()))
 
 
+GEMV_SIZES = {"2000000": 2048, str(1 << 26): 16384}  # the matrix paired with each vector size
+
+
+def run_gemv(m, dtype, reps, log=print):
+    """{config key: GB/s} over the rows-kernel space for y = A x, A m x m."""
+    space = tune.rows_space()
+    w = tune.Workload("gemv", dtype, n=m, m=m, layout="row")
+    t0 = time.time()
+    res = tune.sweep(w, space, reps=reps)
+    log("gemv %dx%d %d configs in %.0f s, best %.1f GB/s" % (m, m, len(res), time.time() - t0, res[0][2]))
+    del w
+    return space, {_key(c): g for c, _, g in res}
+
+
+def analyse_gemv(space, rates, copy_cfg):
+    keys = [k for k in (_key(c) for c in space) if k in rates]
+    cfgs = [dict(k) for k in keys]
+    frac = np.array([rates[k] / PEAK_GBS for k in keys])
+    best = int(np.argmax(frac))
+    one_row = [i for i, c in enumerate(cfgs) if c["rows"] == 1 and c["split"] == 1]
+    b1 = max(one_row, key=lambda i: frac[i])
+    # the paper's mapping with the copy's local size and vector width
+    want = _key(dict(block=copy_cfg["block"], vec=copy_cfg["vec"], rows=1, unroll=1, split=1))
+    paper = rates.get(want)
+    dist = {}
+    for param in ("block", "vec", "rows", "split"):
+        d = {}
+        for v in sorted({c[param] for c in cfgs}):
+            vals = frac[np.array([c[param] == v for c in cfgs])]
+            d[str(v)] = {"median": round(float(np.median(vals)), 3), "max": round(float(vals.max()), 3)}
+        dist[param] = d
+    return {"n_configs": len(keys), "own_best": round(float(frac[best]), 3), "own_best_config": cfgs[best],
+            "one_row_per_group_best": round(float(frac[b1]), 3), "one_row_per_group_best_config": cfgs[b1],
+            "copy_cfg_one_row_per_group": round(paper / PEAK_GBS, 3) if paper else None,
+            "copy_cfg": {"block": copy_cfg["block"], "vec": copy_cfg["vec"]}, "distributions": dist}
+
+
 def run(sizes=(2_000_000, 1 << 26), dtype=torch.float64, reps=5, log=print):
     cus = L.lib.bwla_device_cus()
     space = tune.vector_space(cus)
@@ -54,6 +98,12 @@ def run(sizes=(2_000_000, 1 << 26), dtype=torch.float64, reps=5, log=print):
             log("n=%d %-5s %d configs in %.0f s, best %.1f GB/s" % (n, op, len(res), time.time() - t0, res[0][2]))
             del w
         out["sizes"][str(n)] = analyse(space, rates)
+        m = GEMV_SIZES.get(str(n))
+        if m:
+            gspace, grates = run_gemv(m, dtype, reps, log)
+            out["sizes"][str(n)]["gemv"] = dict(analyse_gemv(gspace, grates, out["sizes"][str(n)]["table2"]["config"]),
+                                                m=m)
+            ops.reset_config()
     ops.reset_config()
     return out
 
@@ -112,6 +162,18 @@ def markdown(res) -> str:
         for op, v in r["copy_vs_ops"].items():
             lines.append("| %s | %.3f | %.3f | %.3f (%d configs) |" % (op, v["spearman_rho"], v["best"],
                                                                       v["best_among_near_copy_best"], v["near_copy_best_configs"]))
+        g = r.get("gemv")
+        if g:
+            lines += ["", "Matrix-vector product, %d x %d, over %d rows-kernel configurations:" % (g["m"], g["m"], g["n_configs"]),
+                      "", "| configuration | fraction of peak |", "|---|---|",
+                      "| own best `%s` | %.3f |" % (g["own_best_config"], g["own_best"]),
+                      "| best with one row per work-group (the paper's mapping) `%s` | %.3f |" % (
+                          g["one_row_per_group_best_config"], g["one_row_per_group_best"]),
+                      "| the paper's mapping with the copy's work-group size and vector width `%s` | %s |" % (
+                          g["copy_cfg"], "%.3f" % g["copy_cfg_one_row_per_group"] if g["copy_cfg_one_row_per_group"] else "-"),
+                      "", "GEMV by parameter: median / max fraction of peak", ""]
+            for p, d in g["distributions"].items():
+                lines.append("- **%s**: " % p + "; ".join("%s: %.2f/%.2f" % (k, v["median"], v["max"]) for k, v in d.items()))
         lines += ["", "Inner product by parameter (Figures 1-4 analogue): median / 90th percentile / max fraction of peak", ""]
         for p, d in r["dot_distributions"].items():
             lines.append("- **%s**: " % p + "; ".join("%s: %.2f/%.2f/%.2f" % (k, v["median"], v["p90"], v["max"])

@@ -97,3 +97,23 @@ def test_study_analysis_on_synthetic_rates():
     assert set(r["dot_distributions"]) == {"increment", "vec", "block", "grid"}
     md = study.markdown({"device": "synthetic", "cus": 256, "configs": len(space), "sizes": {"2000000": r}})
     assert "Table 2" in md and "Spearman" in md
+
+
+def test_study_gemv_analysis_on_synthetic_rates():
+    """GEMV part of the study: with the rate a known function of the
+    configuration, the analysis finds the best configuration overall, the best
+    with one row per work-group, and the paper's mapping at the copy's
+    work-group size and vector width."""
+    from paper_1409_0669_amd import study, tune
+    space = tune.rows_space()
+    rate = lambda c: 1000.0 + 100 * c["rows"] + 10 * c["vec"] + c["block"] / 1024 + (c["split"] == 1)
+    rates = {study._key(c): rate(c) for c in space}
+    g = study.analyse_gemv(space, rates, {"block": 256, "vec": 2, "unroll": 1, "grid": 0, "increment": 0})
+    assert g["n_configs"] == len(space)
+    assert g["own_best_config"]["rows"] == 8 and g["own_best_config"]["vec"] == 16
+    assert g["one_row_per_group_best_config"]["rows"] == 1 and g["one_row_per_group_best_config"]["split"] == 1
+    assert abs(g["copy_cfg_one_row_per_group"] - rate(dict(block=256, vec=2, rows=1, unroll=1, split=1)) / 8000) < 1e-3
+    r = {"table2": {"config": {}, **{op: {"with_copy_cfg": 0.5, "own_best": 0.6} for op in study.OPS}},
+         "copy_vs_ops": {}, "dot_distributions": {}, "gemv": dict(g, m=2048)}
+    md = study.markdown({"device": "synthetic", "cus": 256, "configs": 1, "sizes": {"2000000": r}})
+    assert "one row per work-group" in md and "2048 x 2048" in md
