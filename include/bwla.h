@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BWLA_ABI_VERSION 1
+#define BWLA_ABI_VERSION 2
 
 typedef enum {
     BWLA_OK = 0,
@@ -305,20 +305,28 @@ bwla_status bwla_batch_info(const bwla_batch_plan *p, int64_t *items, int32_t *g
 void bwla_batch_plan_destroy(bwla_batch_plan *p);
 
 /* ---- configuration table ---------------------------------------------------
- * One entry per (op, storage type, size class).  Size class by the bytes the
- * call streams: 0 < 1 MiB, 1 < 16 MiB, 2 < 256 MiB, 3 < 1 GiB, 4 otherwise; pass -1 to
- * set every class.  cfg == NULL restores the defaults.  The table is shared
- * by all threads (mutex-guarded).  If the environment variable BWLA_TUNING
- * names a tuning table, it is loaded before the first call resolves a
- * configuration. */
-bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int size_class, const bwla_config *cfg);
-/* The configuration a call with this op, type and shape would use after
- * defaults are resolved (m = lines, n = line length for GEMV/GER; m ignored
- * for vectors). */
-bwla_status bwla_get_config(bwla_op op, bwla_dtype t, int64_t m, int64_t n, bwla_config *cfg);
+ * One entry per (op, storage type, accumulation mode, size class).  The
+ * accumulation mode matters for the operations that reduce (DOT, NRM2, CG,
+ * GEMV_ROWS, GEMV_COLS): compensated arithmetic adds vector-ALU work per
+ * element, and on gfx950 it runs best with more waves in flight than the
+ * plain form.  COPY, AXPBY and GER always use their plain entry.  Size class
+ * by the bytes the call streams: 0 < 1 MiB, 1 < 16 MiB, 2 < 256 MiB,
+ * 3 < 1 GiB, 4 otherwise.  acc is BWLA_ACC_PLAIN, BWLA_ACC_COMPENSATED or -1
+ * (both); size_class -1 sets every class.  cfg == NULL restores the defaults.
+ * The table is shared by all threads (mutex-guarded).  If the environment
+ * variable BWLA_TUNING names a tuning table, it is loaded before the first
+ * call resolves a configuration.  Workspace sizes (bwla_workspace_size and
+ * the other *_workspace_size calls) cover both accumulation modes under the
+ * current table. */
+bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int acc, int size_class, const bwla_config *cfg);
+/* The configuration a call with this op, type, accumulation mode and shape
+ * would use after defaults are resolved (m = lines, n = line length for
+ * GEMV/GER; m ignored for vectors). */
+bwla_status bwla_get_config(bwla_op op, bwla_dtype t, bwla_acc acc, int64_t m, int64_t n, bwla_config *cfg);
 /* Load a tuning table written by the autotuner: text, one entry per line,
- * "op dtype size_class block vec unroll grid increment rows split", '#'
- * starts a comment. */
+ * "op dtype acc size_class block vec unroll grid increment rows split" (acc
+ * and size_class as for bwla_set_config), '#' starts a comment.  Either every
+ * entry is valid and the whole table is installed, or nothing changes. */
 bwla_status bwla_load_tuning(const char *path);
 
 const char *bwla_status_string(bwla_status st);

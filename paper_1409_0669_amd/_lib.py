@@ -20,6 +20,7 @@ ACC_PLAIN, ACC_COMPENSATED = 0, 1
 INC_GLOBAL, INC_LOCAL = 0, 1
 OP_COPY, OP_AXPBY, OP_DOT, OP_GEMV_ROWS, OP_GEMV_COLS, OP_GER, OP_NRM2, OP_CG = range(8)
 OP_COUNT = 8
+ABI_VERSION = 2  # BWLA_ABI_VERSION of include/bwla.h
 
 STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "INVALID_ARG", ERR_UNSUPPORTED: "UNSUPPORTED",
                 ERR_WORKSPACE: "WORKSPACE", ERR_HIP: "HIP", ERR_NOT_CAPTURABLE: "NOT_CAPTURABLE"}
@@ -74,8 +75,8 @@ SIGNATURES = {
     "bwla_batch_replay": (c_int, [vp, vp]),
     "bwla_batch_info": (c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(dbl)]),
     "bwla_batch_plan_destroy": (None, [vp]),
-    "bwla_set_config": (c_int, [c_int, c_int, c_int, ctypes.POINTER(Config)]),
-    "bwla_get_config": (c_int, [c_int, c_int, i64, i64, ctypes.POINTER(Config)]),
+    "bwla_set_config": (c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(Config)]),
+    "bwla_get_config": (c_int, [c_int, c_int, c_int, i64, i64, ctypes.POINTER(Config)]),
     "bwla_load_tuning": (c_int, [ctypes.c_char_p]),
     "bwla_status_string": (ctypes.c_char_p, [c_int]),
     "bwla_last_error": (ctypes.c_char_p, []),
@@ -100,8 +101,8 @@ def _load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if lib.bwla_abi_version() != 1:
-        raise ImportError("libbwla.so ABI version %d, expected 1" % lib.bwla_abi_version())
+    if lib.bwla_abi_version() != ABI_VERSION:
+        raise ImportError("libbwla.so ABI version %d, expected %d" % (lib.bwla_abi_version(), ABI_VERSION))
     return lib
 
 

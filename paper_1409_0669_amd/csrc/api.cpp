@@ -68,8 +68,9 @@ int device_cus()
 // configuration table
 // ---------------------------------------------------------------------------
 constexpr int kClasses = 5;
+constexpr int kAccs = 2; // plain, compensated: the reductions tune the two apart
 std::mutex g_cfg_mu;
-bwla_config g_table[BWLA_OP_COUNT][3][kClasses]; // zero-initialised: all defaults
+bwla_config g_table[BWLA_OP_COUNT][3][kAccs][kClasses]; // zero-initialised: all defaults
 
 int size_class(double bytes)
 {
@@ -98,11 +99,11 @@ void load_env_table_once()
     });
 }
 
-bwla_config lookup(int op, int t, double bytes)
+bwla_config lookup(int op, int t, int acc, double bytes)
 {
     load_env_table_once();
     std::lock_guard<std::mutex> lk(g_cfg_mu);
-    return g_table[op][t][size_class(bytes)];
+    return g_table[op][t][acc == BWLA_ACC_COMPENSATED][size_class(bytes)];
 }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -153,10 +154,10 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // better and keep the second stage small).
 constexpr int kOpCg = BWLA_OP_CG;
 
-Cfg resolve_vector(int op, int t, int64_t n, std::initializer_list<const void *> ptrs, int nstreams)
+Cfg resolve_vector(int op, int t, int acc, int64_t n, std::initializer_list<const void *> ptrs, int nstreams)
 {
     const bool reduction = op == BWLA_OP_DOT || op == BWLA_OP_NRM2 || op == BWLA_OP_CG;
-    bwla_config u = lookup(op, t, (double)n * dsize(t) * nstreams);
+    bwla_config u = lookup(op, t, reduction ? acc : BWLA_ACC_PLAIN, (double)n * dsize(t) * nstreams);
     Cfg c;
     c.block = u.block ? u.block : 256;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), ptrs);
@@ -184,9 +185,9 @@ Cfg resolve_vector(int op, int t, int64_t n, std::initializer_list<const void *>
     return c;
 }
 
-Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const void *v)
+Cfg resolve_rows(int t, int acc, int64_t L, int64_t K, const void *A, int64_t ld, const void *v)
 {
-    bwla_config u = lookup(BWLA_OP_GEMV_ROWS, t, (double)L * K * dsize(t));
+    bwla_config u = lookup(BWLA_OP_GEMV_ROWS, t, acc, (double)L * K * dsize(t));
     Cfg c;
     c.block = u.block ? u.block : 1024;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A, v}, ld);
@@ -215,10 +216,10 @@ Cfg resolve_rows(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
     return c;
 }
 
-Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const void *v)
+Cfg resolve_cols(int t, int acc, int64_t L, int64_t K, const void *A, int64_t ld, const void *v)
 {
     (void)v; // x is staged element by element: its alignment does not constrain the pack width
-    bwla_config u = lookup(BWLA_OP_GEMV_COLS, t, (double)L * K * dsize(t));
+    bwla_config u = lookup(BWLA_OP_GEMV_COLS, t, acc, (double)L * K * dsize(t));
     Cfg c;
     c.block = u.block ? u.block : 512;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A}, ld);
@@ -243,7 +244,7 @@ Cfg resolve_cols(int t, int64_t L, int64_t K, const void *A, int64_t ld, const v
 
 Cfg resolve_ger(int t, int64_t L, int64_t K, const void *a, const void *b, const void *A, int64_t ld)
 {
-    bwla_config u = lookup(BWLA_OP_GER, t, (double)L * K * dsize(t));
+    bwla_config u = lookup(BWLA_OP_GER, t, BWLA_ACC_PLAIN, (double)L * K * dsize(t));
     Cfg c;
     c.block = u.block ? u.block : 256;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {b, A}, ld);
@@ -271,9 +272,10 @@ size_t ws_cols(const Cfg &c, int64_t K)
     return (size_t)ceil_div(K, 64 * (int64_t)c.vec) * c.split * 64 * c.vec * sizeof(DD);
 }
 
-// Parses a tuning table ("op dtype size_class block vec unroll grid increment
-// rows split" per line, '#' comments) and installs it atomically: either
-// every entry is valid and applied, or nothing changes.
+// Parses a tuning table ("op dtype acc size_class block vec unroll grid
+// increment rows split" per line, '#' comments; acc and size_class -1 mean
+// every mode / class) and installs it atomically: either every entry is valid
+// and applied, or nothing changes.
 bool load_table_file(const char *path, std::string *err)
 {
     FILE *f = fopen(path, "r");
@@ -284,7 +286,7 @@ bool load_table_file(const char *path, std::string *err)
     char line[512];
     int lineno = 0;
     struct Entry {
-        int op, t, k;
+        int op, t, a, k;
         bwla_config c;
     };
     std::vector<Entry> entries;
@@ -294,12 +296,12 @@ bool load_table_file(const char *path, std::string *err)
         if (hash)
             *hash = 0;
         Entry e{};
-        int got = sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &e.op, &e.t, &e.k, &e.c.block, &e.c.vec,
-                         &e.c.unroll, &e.c.grid, &e.c.increment, &e.c.rows, &e.c.split);
+        int got = sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d", &e.op, &e.t, &e.a, &e.k, &e.c.block,
+                         &e.c.vec, &e.c.unroll, &e.c.grid, &e.c.increment, &e.c.rows, &e.c.split);
         if (got <= 0)
             continue; // blank or comment line
-        if (got != 10 || e.op < 0 || e.op >= BWLA_OP_COUNT || !valid_dtype(e.t) || e.k < -1 ||
-            e.k >= kClasses || check_cfg(e.c) != BWLA_OK) {
+        if (got != 11 || e.op < 0 || e.op >= BWLA_OP_COUNT || !valid_dtype(e.t) || e.a < -1 ||
+            e.a >= kAccs || e.k < -1 || e.k >= kClasses || check_cfg(e.c) != BWLA_OK) {
             fclose(f);
             char buf[600];
             snprintf(buf, sizeof buf, "%s:%d: malformed tuning entry", path, lineno);
@@ -311,9 +313,10 @@ bool load_table_file(const char *path, std::string *err)
     fclose(f);
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     for (const Entry &e : entries)
-        for (int k = 0; k < kClasses; ++k)
-            if (e.k < 0 || e.k == k)
-                g_table[e.op][e.t][k] = e.c;
+        for (int a = 0; a < kAccs; ++a)
+            for (int k = 0; k < kClasses; ++k)
+                if ((e.a < 0 || e.a == a) && (e.k < 0 || e.k == k))
+                    g_table[e.op][e.t][a][k] = e.c;
     return true;
 }
 
@@ -454,7 +457,7 @@ bwla_status bwla_copy(bwla_dtype t, int64_t n, const void *y, void *x, void *str
         return BWLA_OK;
     if (overlaps(sx, sy))
         return fail(BWLA_ERR_INVALID_ARG, "x partially overlaps y");
-    Cfg c = resolve_vector(BWLA_OP_COPY, t, n, {x, y}, 2);
+    Cfg c = resolve_vector(BWLA_OP_COPY, t, BWLA_ACC_PLAIN, n, {x, y}, 2);
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         return launch_copy<T>(n, y, x, c, (hipStream_t)stream);
@@ -481,7 +484,7 @@ bwla_status bwla_axpby(bwla_dtype t, int64_t n, double alpha, const void *alpha_
     Span sxa = span(x, b);
     if ((alpha_dev && overlaps(sxa, span(alpha_dev, cs))) || (beta_dev && overlaps(sxa, span(beta_dev, cs))))
         return fail(BWLA_ERR_INVALID_ARG, "a device scalar lies inside the output x");
-    Cfg c = resolve_vector(BWLA_OP_AXPBY, t, n, {x, y, z}, 3);
+    Cfg c = resolve_vector(BWLA_OP_AXPBY, t, BWLA_ACC_PLAIN, n, {x, y, z}, 3);
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         return launch_axpby<T>(n, alpha, alpha_dev, y, beta, beta_dev, z, x, c, (hipStream_t)stream);
@@ -500,7 +503,7 @@ static bwla_status reduce_common(bwla_dtype t, bwla_acc acc, int mode, int64_t n
     Cfg c{};
     size_t need = 0;
     if (packed) {
-        c = resolve_vector(two ? BWLA_OP_DOT : BWLA_OP_NRM2, t, n, {x, y}, two ? 2 : 1);
+        c = resolve_vector(two ? BWLA_OP_DOT : BWLA_OP_NRM2, t, acc, n, {x, y}, two ? 2 : 1);
         need = n > 0 ? ws_dot(c) : 0;
     } else {
         need = n > 0 ? ws_strided(n) : 0;
@@ -649,7 +652,7 @@ bwla_status bwla_scal(bwla_dtype t, int64_t n, double alpha, const void *alpha_d
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         if (incx == 1) // reads and writes one stream each, as the copy
-            return launch_scal<T>(n, alpha, alpha_dev, x, x, resolve_vector(BWLA_OP_COPY, t, n, {x}, 2), s);
+            return launch_scal<T>(n, alpha, alpha_dev, x, x, resolve_vector(BWLA_OP_COPY, t, BWLA_ACC_PLAIN, n, {x}, 2), s);
         return launch_strided_elem<T>(kElemScal, n, alpha, alpha_dev, 0.0, nullptr, x, incx, nullptr, 0, x, incx,
                                       strided_grid(n, false), s);
     });
@@ -689,9 +692,9 @@ static size_t gemv_ws(const GemvPlan &g, const Cfg &c, bool with_dot, size_t *dp
     return base + (size_t)gemv_dot_parts(g.rows, g.L, g.K, c) * sizeof(DD);
 }
 
-static Cfg gemv_cfg(bwla_dtype t, const GemvPlan &g, const void *A, int64_t lda, const void *x)
+static Cfg gemv_cfg(bwla_dtype t, int acc, const GemvPlan &g, const void *A, int64_t lda, const void *x)
 {
-    return g.rows ? resolve_rows(t, g.L, g.K, A, lda, x) : resolve_cols(t, g.L, g.K, A, lda, x);
+    return g.rows ? resolve_rows(t, acc, g.L, g.K, A, lda, x) : resolve_cols(t, acc, g.L, g.K, A, lda, x);
 }
 
 // Shared body of bwla_gemv and bwla_gemv_dot (w == NULL: no epilogue).
@@ -755,7 +758,7 @@ static bwla_status gemv_common(bwla_dtype t, bwla_acc acc, bwla_layout layout, i
     }
     const bool comp = acc == BWLA_ACC_COMPENSATED;
     const int of64 = out_t == BWLA_F64, df64 = dot_t == BWLA_F64;
-    Cfg c = gemv_cfg(t, g, A, lda, x);
+    Cfg c = gemv_cfg(t, acc, g, A, lda, x);
     size_t off = 0;
     const size_t need = gemv_ws(g, c, fused, &off);
     if (need && (!ws || ws_bytes < need))
@@ -804,11 +807,12 @@ bwla_status bwla_gemv_dot_workspace_size(bwla_dtype t, bwla_layout layout, int t
     GemvPlan g = gemv_plan(layout, trans, m, n);
     if (g.out_len == 0 || g.in_len == 0)
         return BWLA_OK; // only fills run
-    size_t best = 0; // largest over the pack widths the call could end up with
-    for (int v = 1; v <= 16; v <<= 1) {
-        const void *fake = (const void *)(uintptr_t)(v * dsize(t));
-        best = std::max(best, gemv_ws(g, gemv_cfg(t, g, fake, v, fake), true, nullptr));
-    }
+    size_t best = 0; // largest over the pack widths and accumulation modes the call could use
+    for (int acc = 0; acc < kAccs; ++acc)
+        for (int v = 1; v <= 16; v <<= 1) {
+            const void *fake = (const void *)(uintptr_t)(v * dsize(t));
+            best = std::max(best, gemv_ws(g, gemv_cfg(t, acc, g, fake, v, fake), true, nullptr));
+        }
     *bytes = best;
     return BWLA_OK;
 }
@@ -865,7 +869,7 @@ bwla_status bwla_gemv_ex(bwla_dtype t, bwla_acc acc, bwla_layout layout, int tra
     Cfg c{};
     size_t need = off_g;
     if (g.in_len > 0) {
-        c = gemv_cfg(t, g, A, lda, xs);
+        c = gemv_cfg(t, acc, g, A, lda, xs);
         need += gemv_ws(g, c, false, nullptr);
     }
     if (!ws || ws_bytes < need)
@@ -929,10 +933,11 @@ bwla_status bwla_gemv_ex_workspace_size(bwla_dtype t, bwla_dtype out_t, bwla_lay
     size_t best = align256(align256((size_t)g.in_len * dsize(t)) + (size_t)g.out_len * os);
     size_t gw = 0;
     if (g.in_len > 0)
-        for (int v = 1; v <= 16; v <<= 1) {
-            const void *fake = (const void *)(uintptr_t)(v * dsize(t));
-            gw = std::max(gw, gemv_ws(g, gemv_cfg(t, g, fake, v, fake), false, nullptr));
-        }
+        for (int acc = 0; acc < kAccs; ++acc)
+            for (int v = 1; v <= 16; v <<= 1) {
+                const void *fake = (const void *)(uintptr_t)(v * dsize(t));
+                gw = std::max(gw, gemv_ws(g, gemv_cfg(t, acc, g, fake, v, fake), false, nullptr));
+            }
     *bytes = best + gw;
     return BWLA_OK;
 }
@@ -972,7 +977,7 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha, 
                            void *x, const void *p, void *r, const void *q, bwla_dtype out_t, void *out,
                            void *ws, size_t ws_bytes, void *stream)
 {
-    Cfg c = resolve_vector(kOpCg, t, n, {x, p, r, q}, 6);
+    Cfg c = resolve_vector(kOpCg, t, acc, n, {x, p, r, q}, 6);
     const size_t need = n > 0 ? ws_dot(c) : 0;
     bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
     if (st)
@@ -999,7 +1004,8 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha, 
 bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_layout layout, int trans,
                                 int64_t m, int64_t n, size_t *bytes)
 {
-    (void)acc;
+    if (acc != BWLA_ACC_PLAIN && acc != BWLA_ACC_COMPENSATED)
+        return fail(BWLA_ERR_UNSUPPORTED, "accumulation mode %d", acc);
     if (!bytes)
         return fail(BWLA_ERR_INVALID_ARG, "bytes is NULL");
     if (!valid_dtype(t))
@@ -1010,34 +1016,38 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
     // The pack width a call ends up with depends on pointer alignment, and the
     // default grid and split depend on the pack width, so size for the largest
     // requirement over every width the call could use.  A fake address
-    // v*sizeof(T) (and line stride v) is aligned to exactly v elements.
+    // v*sizeof(T) (and line stride v) is aligned to exactly v elements.  The
+    // size also serves the other accumulation mode, whose table entry may
+    // differ, so a buffer sized once serves both.
     size_t best = 0;
-    for (int v = 1; v <= 16; v <<= 1) {
-        const void *fake = (const void *)(uintptr_t)(v * dsize(t));
-        switch (op) {
-        case BWLA_OP_DOT: // dot, nrm2, asum (any increments) and the CG update share one sizing
-        case BWLA_OP_NRM2:
-        case BWLA_OP_CG:
-            best = std::max(best, ws_strided(n));
-            best = std::max(best, ws_dot(resolve_vector(BWLA_OP_DOT, t, n, {fake}, 2)));
-            best = std::max(best, ws_dot(resolve_vector(BWLA_OP_NRM2, t, n, {fake}, 1)));
-            best = std::max(best, ws_dot(resolve_vector(kOpCg, t, n, {fake}, 6)));
-            break;
-        case BWLA_OP_GEMV_ROWS:
-        case BWLA_OP_GEMV_COLS: {
-            if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
-                return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
-            GemvPlan g = gemv_plan(layout, trans, m, n);
-            if (g.out_len == 0 || g.in_len == 0)
-                break; // no kernel runs
-            if (g.rows)
-                best = std::max(best, ws_rows(resolve_rows(t, g.L, g.K, fake, v, fake), g.L));
-            else
-                best = std::max(best, ws_cols(resolve_cols(t, g.L, g.K, fake, v, fake), g.K));
-            break;
-        }
-        default:
-            break;
+    for (int a = 0; a < kAccs; ++a) {
+        for (int v = 1; v <= 16; v <<= 1) {
+            const void *fake = (const void *)(uintptr_t)(v * dsize(t));
+            switch (op) {
+            case BWLA_OP_DOT: // dot, nrm2, asum (any increments) and the CG update share one sizing
+            case BWLA_OP_NRM2:
+            case BWLA_OP_CG:
+                best = std::max(best, ws_strided(n));
+                best = std::max(best, ws_dot(resolve_vector(BWLA_OP_DOT, t, a, n, {fake}, 2)));
+                best = std::max(best, ws_dot(resolve_vector(BWLA_OP_NRM2, t, a, n, {fake}, 1)));
+                best = std::max(best, ws_dot(resolve_vector(kOpCg, t, a, n, {fake}, 6)));
+                break;
+            case BWLA_OP_GEMV_ROWS:
+            case BWLA_OP_GEMV_COLS: {
+                if (layout != BWLA_ROW_MAJOR && layout != BWLA_COL_MAJOR)
+                    return fail(BWLA_ERR_INVALID_ARG, "layout %d", layout);
+                GemvPlan g = gemv_plan(layout, trans, m, n);
+                if (g.out_len == 0 || g.in_len == 0)
+                    break; // no kernel runs
+                if (g.rows)
+                    best = std::max(best, ws_rows(resolve_rows(t, a, g.L, g.K, fake, v, fake), g.L));
+                else
+                    best = std::max(best, ws_cols(resolve_cols(t, a, g.L, g.K, fake, v, fake), g.K));
+                break;
+            }
+            default:
+                break;
+            }
         }
     }
     *bytes = best;
@@ -1047,12 +1057,14 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
 // ---------------------------------------------------------------------------
 // configuration entry points
 // ---------------------------------------------------------------------------
-bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int size_class, const bwla_config *cfg)
+bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int acc, int size_class, const bwla_config *cfg)
 {
     if (op < 0 || op >= BWLA_OP_COUNT)
         return fail(BWLA_ERR_INVALID_ARG, "op %d", op);
     if (!valid_dtype(t))
         return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (acc < -1 || acc >= kAccs)
+        return fail(BWLA_ERR_INVALID_ARG, "accumulation mode %d", acc);
     if (size_class < -1 || size_class >= kClasses)
         return fail(BWLA_ERR_INVALID_ARG, "size class %d", size_class);
     bwla_config c{};
@@ -1063,29 +1075,32 @@ bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int size_class, const bwla
         c = *cfg;
     }
     std::lock_guard<std::mutex> lk(g_cfg_mu);
-    for (int k = 0; k < kClasses; ++k)
-        if (size_class < 0 || size_class == k)
-            g_table[op][t][k] = c;
+    for (int a = 0; a < kAccs; ++a)
+        for (int k = 0; k < kClasses; ++k)
+            if ((acc < 0 || acc == a) && (size_class < 0 || size_class == k))
+                g_table[op][t][a][k] = c;
     return BWLA_OK;
 }
 
-bwla_status bwla_get_config(bwla_op op, bwla_dtype t, int64_t m, int64_t n, bwla_config *cfg)
+bwla_status bwla_get_config(bwla_op op, bwla_dtype t, bwla_acc acc, int64_t m, int64_t n, bwla_config *cfg)
 {
     if (!cfg)
         return fail(BWLA_ERR_INVALID_ARG, "cfg is NULL");
     if (!valid_dtype(t))
         return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (acc != BWLA_ACC_PLAIN && acc != BWLA_ACC_COMPENSATED)
+        return fail(BWLA_ERR_UNSUPPORTED, "accumulation mode %d", acc);
     if (m < 0 || n < 0)
         return fail(BWLA_ERR_INVALID_ARG, "negative size");
     Cfg c;
     switch (op) {
-    case BWLA_OP_COPY: c = resolve_vector(op, t, n, {}, 2); break;
-    case BWLA_OP_AXPBY: c = resolve_vector(op, t, n, {}, 3); break;
-    case BWLA_OP_DOT: c = resolve_vector(op, t, n, {}, 2); break;
-    case BWLA_OP_NRM2: c = resolve_vector(op, t, n, {}, 1); break;
-    case BWLA_OP_CG: c = resolve_vector(op, t, n, {}, 6); break;
-    case BWLA_OP_GEMV_ROWS: c = resolve_rows(t, m, n, nullptr, 0, nullptr); break;
-    case BWLA_OP_GEMV_COLS: c = resolve_cols(t, m, n, nullptr, 0, nullptr); break;
+    case BWLA_OP_COPY: c = resolve_vector(op, t, acc, n, {}, 2); break;
+    case BWLA_OP_AXPBY: c = resolve_vector(op, t, acc, n, {}, 3); break;
+    case BWLA_OP_DOT: c = resolve_vector(op, t, acc, n, {}, 2); break;
+    case BWLA_OP_NRM2: c = resolve_vector(op, t, acc, n, {}, 1); break;
+    case BWLA_OP_CG: c = resolve_vector(op, t, acc, n, {}, 6); break;
+    case BWLA_OP_GEMV_ROWS: c = resolve_rows(t, acc, m, n, nullptr, 0, nullptr); break;
+    case BWLA_OP_GEMV_COLS: c = resolve_cols(t, acc, m, n, nullptr, 0, nullptr); break;
     case BWLA_OP_GER: c = resolve_ger(t, m, n, nullptr, nullptr, nullptr, 0); break;
     default: return fail(BWLA_ERR_INVALID_ARG, "op %d", op);
     }

@@ -341,18 +341,20 @@ def cg_update(alpha: float, x: torch.Tensor, p: torch.Tensor, r: torch.Tensor, q
 # ---------------------------------------------------------------------------
 # configuration
 # ---------------------------------------------------------------------------
-def set_config(op: int, dtype: torch.dtype, size_class: int = -1, **fields) -> None:
-    """Set the configuration of (op, dtype, size class); no fields = defaults."""
+def set_config(op: int, dtype: torch.dtype, size_class: int = -1, acc=None, **fields) -> None:
+    """Set the configuration of (op, dtype, accumulation mode, size class); no
+    fields = defaults.  acc None sets both accumulation modes."""
+    a = -1 if acc is None else _ACC[acc]
     if fields:
         c = L.Config(**{k: int(v) for k, v in fields.items()})
-        check(lib.bwla_set_config(op, dtype_code(dtype), size_class, ctypes.byref(c)))
+        check(lib.bwla_set_config(op, dtype_code(dtype), a, size_class, ctypes.byref(c)))
     else:
-        check(lib.bwla_set_config(op, dtype_code(dtype), size_class, None))
+        check(lib.bwla_set_config(op, dtype_code(dtype), a, size_class, None))
 
 
-def get_config(op: int, dtype: torch.dtype, m: int = 0, n: int = 0) -> dict:
+def get_config(op: int, dtype: torch.dtype, m: int = 0, n: int = 0, acc="plain") -> dict:
     c = L.Config()
-    check(lib.bwla_get_config(op, dtype_code(dtype), m, n, ctypes.byref(c)))
+    check(lib.bwla_get_config(op, dtype_code(dtype), _ACC[acc], m, n, ctypes.byref(c)))
     return c.as_dict()
 
 

@@ -101,12 +101,22 @@ def time_ms(fn, reps: int = 10, warmup: int = 2) -> float:
     return statistics.median(times)
 
 
-class Workload:
-    """Device operands of one tuned operation and its algorithmic bytes."""
+# operations whose table entries are kept per accumulation mode
+REDUCING = ("dot", "nrm2", "cg", "gemv")
 
-    def __init__(self, op: str, dtype: torch.dtype, n: int = 0, m: int = 0, layout: str = "row"):
+
+class Workload:
+    """Device operands of one tuned operation and its algorithmic bytes.  acc
+    is the accumulation mode the reducing operations run with; the table
+    entry they are tuned into is that mode's (elementwise operations have one
+    entry for both modes)."""
+
+    def __init__(self, op: str, dtype: torch.dtype, n: int = 0, m: int = 0, layout: str = "row",
+                 acc: str = "plain"):
         import workloads as W
         self.op, self.dtype, self.n, self.m, self.layout = op, dtype, n, m, layout
+        self.acc = acc
+        self.table_acc = acc if op in REDUCING else None
         name = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}[dtype]
         s = torch.tensor([], dtype=dtype).element_size()
         if op in ("copy", "axpby", "dot", "nrm2", "cg"):
@@ -141,24 +151,29 @@ class Workload:
         elif o == "axpby":
             ops.axpby(0.75, self.y, -1.25, self.z, out=self.x)
         elif o == "dot":
-            ops.dot(self.y, self.z)
+            ops.dot(self.y, self.z, acc=self.acc)
         elif o == "nrm2":
-            ops.nrm2(self.y)
+            ops.nrm2(self.y, acc=self.acc)
         elif o == "cg":
             # a tiny step keeps the iterates bounded over many repetitions
-            ops.cg_update(1e-9, self.x, self.y, self.r, self.z)
+            ops.cg_update(1e-9, self.x, self.y, self.r, self.z, acc=self.acc)
         elif o == "ger":
             ops.ger(self.u, self.v, self.A)
         else:
-            ops.gemv(self.A, self.x, out=self.yv)
+            ops.gemv(self.A, self.x, acc=self.acc, out=self.yv)
 
 
-def sweep(w: Workload, candidates, reps: int = 8, log=None):
+def sweep(w: Workload, candidates, reps: int = 8, log=None, refine: int = 0, refine_rounds: int = 5):
     """Time every candidate configuration on workload w.  Returns a list of
-    (config, ms, GB/s) sorted by speed."""
+    (config, ms, GB/s) sorted by speed.
+
+    With refine = k > 0 the k fastest are timed again, round-robin over
+    `refine_rounds` rounds of `reps` runs each, and ranked by the median of all
+    their runs: the fastest of hundreds of short measurements is partly
+    noise, and interleaving spreads any drift of the device over all k."""
     res = []
     for cfg in candidates:
-        ops.set_config(w.table_op, w.dtype, w.cls, **cfg)
+        ops.set_config(w.table_op, w.dtype, w.cls, acc=w.table_acc, **cfg)
         try:
             ms = time_ms(w.run, reps=reps)
         except L.BwlaError as e:  # e.g. a configuration the shape cannot use
@@ -166,22 +181,36 @@ def sweep(w: Workload, candidates, reps: int = 8, log=None):
                 log("skip %s: %s" % (cfg, e))
             continue
         res.append((cfg, ms, w.bytes / (ms * 1e-3) / 1e9))
-    ops.set_config(w.table_op, w.dtype, w.cls)
     res.sort(key=lambda r: r[1])
+    if refine > 1 and len(res) > 1:
+        top = [r[0] for r in res[:refine]]
+        runs = {i: [] for i in range(len(top))}
+        for _ in range(refine_rounds):
+            for i, cfg in enumerate(top):
+                ops.set_config(w.table_op, w.dtype, w.cls, acc=w.table_acc, **cfg)
+                runs[i].append(time_ms(w.run, reps=reps))
+        again = sorted(((top[i], statistics.median(t), w.bytes / (statistics.median(t) * 1e-3) / 1e9)
+                        for i, t in runs.items()), key=lambda r: r[1])
+        res = again + res[refine:]
+    ops.set_config(w.table_op, w.dtype, w.cls, acc=w.table_acc)
     return res
 
 
+ACC_CODE = {None: -1, "plain": L.ACC_PLAIN, "compensated": L.ACC_COMPENSATED}
+
+
 def write_table(entries, path: str) -> None:
-    """entries: list of (op code, dtype, size class, config dict)."""
+    """entries: list of (op code, dtype, acc, size class, config dict); acc is
+    "plain", "compensated" or None (both modes share the entry)."""
     code = {torch.float64: L.F64, torch.float32: L.F32, torch.bfloat16: L.BF16}
     with open(path, "w") as f:
-        f.write("# bwla tuning table: op dtype size_class block vec unroll grid increment rows split\n")
+        f.write("# bwla tuning table: op dtype acc size_class block vec unroll grid increment rows split\n")
         f.write("# written %s on %s\n" % (time.strftime("%Y-%m-%d %H:%M:%S"),
                                           torch.cuda.get_device_name() if torch.cuda.is_available() else "?"))
-        for op, dt, cls, c in entries:
-            f.write("%d %d %d %d %d %d %d %d %d %d\n" % (
-                op, code[dt], cls, c.get("block", 0), c.get("vec", 0), c.get("unroll", 0), c.get("grid", 0),
-                c.get("increment", 0), c.get("rows", 0), c.get("split", 0)))
+        for op, dt, acc, cls, c in entries:
+            f.write("%d %d %d %d %d %d %d %d %d %d %d\n" % (
+                op, code[dt], ACC_CODE[acc], cls, c.get("block", 0), c.get("vec", 0), c.get("unroll", 0),
+                c.get("grid", 0), c.get("increment", 0), c.get("rows", 0), c.get("split", 0)))
 
 
 def copy_proxy(results: dict) -> dict:
@@ -240,58 +269,60 @@ def _ger_candidates(dtype, quick):
 
 
 def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
-    """Sweep every operation, storage type and size class; return the table
-    entries and a report (best and default rates, copy proxy)."""
+    """Sweep every operation, storage type, accumulation mode (for the
+    reducing operations) and size class; return the table entries and a
+    report (best and default rates, copy proxy)."""
     cus = L.lib.bwla_device_cus()
     ops.reset_config()
     entries, report = [], {"device": torch.cuda.get_device_name(), "cus": cus, "results": [], "copy_proxy": {}}
     vec_sizes = (1 << 16, 1 << 20, 1 << 23, 1 << 25, 1 << 26)
+    refine = 0 if quick else 6
+
+    def record(w, res, default_ms, **where):
+        rec = {"op": w.op if w.op != "gemv" else "gemv_" + w.layout, "dtype": where.pop("dn"),
+               "acc": w.table_acc, "class": w.cls, "bytes": w.bytes, "best": res[0][0],
+               "best_gbs": round(res[0][2], 1), "default_gbs": round(w.bytes / (default_ms * 1e-3) / 1e9, 1)}
+        rec.update(where)
+        report["results"].append(rec)
+        log("%-9s %-4s %-11s %-13s class %d best %7.1f GB/s default %7.1f GB/s %s" % (
+            rec["op"], rec["dtype"], w.table_acc or "", "x".join(str(v) for v in where.values()), w.cls,
+            res[0][2], rec["default_gbs"], res[0][0]))
+
     for dn in dtypes:
         dt = _DT[dn]
         cands = _vector_candidates(dt, cus, quick)
         cands_red = _vector_candidates(dt, cus, quick, reduction=True)
         proxy_in = {}
         for op in ("copy", "axpby", "dot", "nrm2", "cg"):
-            best_for_class = {}
-            for n in vec_sizes:
-                w = Workload(op, dt, n=n)
-                default_ms = time_ms(w.run, reps=10)
-                res = sweep(w, cands_red if op in ("dot", "nrm2") else cands, reps=6)
-                best = res[0]
-                best_for_class[w.cls] = best[0]  # larger sizes overwrite smaller ones in the same class
-                report["results"].append({"op": op, "dtype": dn, "n": n, "class": w.cls, "bytes": w.bytes,
-                                          "best": best[0], "best_gbs": round(best[2], 1),
-                                          "default_gbs": round(w.bytes / (default_ms * 1e-3) / 1e9, 1)})
-                log("%-5s %-4s n=%-9d class %d best %7.1f GB/s default %7.1f GB/s %s" % (
-                    op, dn, n, w.cls, best[2], w.bytes / (default_ms * 1e-3) / 1e9, best[0]))
-                if n == vec_sizes[-1] and op != "cg":
-                    proxy_in[op] = res
-                del w
-            for cls, cfg in best_for_class.items():
-                entries.append((Workload_table_op(op), dt, cls, cfg))
+            for acc in (("plain", "compensated") if op in REDUCING else ("plain",)):
+                best_for_class = {}
+                for n in vec_sizes:
+                    w = Workload(op, dt, n=n, acc=acc)
+                    default_ms = time_ms(w.run, reps=10)
+                    res = sweep(w, cands_red if op in ("dot", "nrm2") else cands, reps=6, refine=refine)
+                    best_for_class[w.cls] = res[0][0]  # larger sizes overwrite smaller ones in the same class
+                    record(w, res, default_ms, dn=dn, n=n)
+                    if n == vec_sizes[-1] and op != "cg" and acc == "plain":
+                        proxy_in[op] = res
+                    del w
+                for cls, cfg in best_for_class.items():
+                    entries.append((Workload_table_op(op), dt, acc if op in REDUCING else None, cls, cfg))
         report["copy_proxy"][dn] = copy_proxy(proxy_in)
         for (m, n) in ((1024, 1024), (4096, 4096), (8192, 8192), (16384, 16384)):
             for layout, cands_g in (("row", _rows_candidates(dt, quick)), ("col", _cols_candidates(dt, quick))):
-                w = Workload("gemv", dt, n=n, m=m, layout=layout)
-                default_ms = time_ms(w.run, reps=10)
-                res = sweep(w, cands_g, reps=6)
-                entries.append((w.table_op, dt, w.cls, res[0][0]))
-                report["results"].append({"op": "gemv_" + layout, "dtype": dn, "m": m, "n": n, "class": w.cls,
-                                          "bytes": w.bytes, "best": res[0][0], "best_gbs": round(res[0][2], 1),
-                                          "default_gbs": round(w.bytes / (default_ms * 1e-3) / 1e9, 1)})
-                log("gemv %s %-4s %dx%d class %d best %7.1f GB/s default %7.1f GB/s %s" % (
-                    layout, dn, m, n, w.cls, res[0][2], w.bytes / (default_ms * 1e-3) / 1e9, res[0][0]))
-                del w
+                for acc in ("plain", "compensated"):
+                    w = Workload("gemv", dt, n=n, m=m, layout=layout, acc=acc)
+                    default_ms = time_ms(w.run, reps=10)
+                    res = sweep(w, cands_g, reps=6, refine=refine)
+                    entries.append((w.table_op, dt, acc, w.cls, res[0][0]))
+                    record(w, res, default_ms, dn=dn, m=m, n=n)
+                    del w
         for (m, n) in ((4096, 4096), (16384, 16384)):
             w = Workload("ger", dt, n=n, m=m)
             default_ms = time_ms(w.run, reps=10)
-            res = sweep(w, _ger_candidates(dt, quick), reps=6)
-            entries.append((L.OP_GER, dt, w.cls, res[0][0]))
-            report["results"].append({"op": "ger", "dtype": dn, "m": m, "n": n, "class": w.cls, "bytes": w.bytes,
-                                      "best": res[0][0], "best_gbs": round(res[0][2], 1),
-                                      "default_gbs": round(w.bytes / (default_ms * 1e-3) / 1e9, 1)})
-            log("ger %-4s %dx%d class %d best %7.1f GB/s default %7.1f GB/s %s" % (
-                dn, m, n, w.cls, res[0][2], w.bytes / (default_ms * 1e-3) / 1e9, res[0][0]))
+            res = sweep(w, _ger_candidates(dt, quick), reps=6, refine=refine)
+            entries.append((L.OP_GER, dt, None, w.cls, res[0][0]))
+            record(w, res, default_ms, dn=dn, m=m, n=n)
             del w
     return entries, report
 

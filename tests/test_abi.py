@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version_and_strings(L):
-    assert L.lib.bwla_abi_version() == 1
+    assert L.lib.bwla_abi_version() == L.ABI_VERSION == 2
     for st, name in [(0, b"ok"), (1, b"invalid argument"), (3, b"workspace too small"), (4, b"HIP error")]:
         assert L.lib.bwla_status_string(st) == name
 
@@ -114,47 +114,100 @@ def test_workspace_sizes(L):
 def test_config_table(L):
     lib = L.lib
     c = L.Config(block=512, vec=4, unroll=2, grid=1024, increment=1, rows=0, split=0)
-    assert lib.bwla_set_config(L.OP_AXPBY, 1, -1, ctypes.byref(c)) == L.OK
+    assert lib.bwla_set_config(L.OP_AXPBY, 1, -1, -1, ctypes.byref(c)) == L.OK
     got = L.Config()
-    assert lib.bwla_get_config(L.OP_AXPBY, 1, 0, 1000, ctypes.byref(got)) == L.OK
+    assert lib.bwla_get_config(L.OP_AXPBY, 1, 0, 0, 1000, ctypes.byref(got)) == L.OK
     assert (got.block, got.vec, got.unroll, got.grid, got.increment) == (512, 4, 2, 1024, 1)
-    assert lib.bwla_set_config(L.OP_AXPBY, 1, -1, None) == L.OK
-    assert lib.bwla_get_config(L.OP_AXPBY, 1, 0, 1000, ctypes.byref(got)) == L.OK
+    assert lib.bwla_set_config(L.OP_AXPBY, 1, -1, -1, None) == L.OK
+    assert lib.bwla_get_config(L.OP_AXPBY, 1, 0, 0, 1000, ctypes.byref(got)) == L.OK
     assert (got.block, got.vec) == (256, 4)
     bad = L.Config(block=100)
-    assert lib.bwla_set_config(L.OP_COPY, 0, 0, ctypes.byref(bad)) == L.ERR_INVALID_ARG
+    assert lib.bwla_set_config(L.OP_COPY, 0, -1, 0, ctypes.byref(bad)) == L.ERR_INVALID_ARG
     bad = L.Config(vec=3)
-    assert lib.bwla_set_config(L.OP_COPY, 0, 0, ctypes.byref(bad)) == L.ERR_INVALID_ARG
-    assert lib.bwla_set_config(99, 0, 0, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_set_config(L.OP_COPY, 0, -1, 0, ctypes.byref(bad)) == L.ERR_INVALID_ARG
+    assert lib.bwla_set_config(99, 0, -1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_set_config(L.OP_DOT, 0, 2, 0, None) == L.ERR_INVALID_ARG      # no such mode
+    assert lib.bwla_get_config(L.OP_DOT, 0, 2, 0, 10, ctypes.byref(got)) == L.ERR_UNSUPPORTED
     # eight packs in flight: kept for the reductions, four for everything else
     eight = L.Config(unroll=8)
     for op, want in ((L.OP_DOT, 8), (L.OP_NRM2, 8), (L.OP_COPY, 4), (L.OP_AXPBY, 4), (L.OP_CG, 4),
                      (L.OP_GEMV_COLS, 8), (L.OP_GEMV_ROWS, 1)):
-        assert lib.bwla_set_config(op, 0, -1, ctypes.byref(eight)) == L.OK
-        assert lib.bwla_get_config(op, 0, 1024, 1 << 20, ctypes.byref(got)) == L.OK
+        assert lib.bwla_set_config(op, 0, -1, -1, ctypes.byref(eight)) == L.OK
+        assert lib.bwla_get_config(op, 0, 0, 1024, 1 << 20, ctypes.byref(got)) == L.OK
         assert got.unroll == want, (op, got.unroll)
-        assert lib.bwla_set_config(op, 0, -1, None) == L.OK
-    assert lib.bwla_set_config(L.OP_DOT, 0, -1, ctypes.byref(L.Config(unroll=3))) == L.ERR_INVALID_ARG
+        assert lib.bwla_set_config(op, 0, -1, -1, None) == L.OK
+    assert lib.bwla_set_config(L.OP_DOT, 0, -1, -1, ctypes.byref(L.Config(unroll=3))) == L.ERR_INVALID_ARG
+
+
+def test_config_table_keeps_the_accumulation_modes_apart(L):
+    """The reducing operations have one entry per accumulation mode; the
+    elementwise ones read their plain entry whatever mode a caller names."""
+    lib = L.lib
+    got = L.Config()
+    plain, comp = L.Config(block=1024, vec=2, unroll=4, grid=256), L.Config(block=256, vec=1, unroll=2, grid=512)
+    try:
+        for op in (L.OP_DOT, L.OP_NRM2, L.OP_CG):
+            assert lib.bwla_set_config(op, 1, L.ACC_PLAIN, -1, ctypes.byref(plain)) == L.OK
+            assert lib.bwla_set_config(op, 1, L.ACC_COMPENSATED, -1, ctypes.byref(comp)) == L.OK
+            for acc, want in ((L.ACC_PLAIN, plain), (L.ACC_COMPENSATED, comp)):
+                assert lib.bwla_get_config(op, 1, acc, 0, 1 << 22, ctypes.byref(got)) == L.OK
+                assert (got.block, got.vec, got.unroll, got.grid) == (want.block, want.vec, want.unroll,
+                                                                       want.grid), (op, acc)
+        rows_p, rows_c = L.Config(block=512, vec=4, rows=4, split=1), L.Config(block=256, vec=4, rows=2, split=2)
+        assert lib.bwla_set_config(L.OP_GEMV_ROWS, 1, L.ACC_PLAIN, -1, ctypes.byref(rows_p)) == L.OK
+        assert lib.bwla_set_config(L.OP_GEMV_ROWS, 1, L.ACC_COMPENSATED, -1, ctypes.byref(rows_c)) == L.OK
+        lib.bwla_get_config(L.OP_GEMV_ROWS, 1, L.ACC_PLAIN, 4096, 4096, ctypes.byref(got))
+        assert (got.block, got.rows, got.split) == (512, 4, 1)
+        lib.bwla_get_config(L.OP_GEMV_ROWS, 1, L.ACC_COMPENSATED, 4096, 4096, ctypes.byref(got))
+        assert (got.block, got.rows, got.split) == (256, 2, 2)
+        # the workspace size covers both modes: a compensated entry with more
+        # work-groups raises the size asked for in plain mode too
+        b_small, b_big = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.bwla_set_config(L.OP_DOT, 1, -1, -1, ctypes.byref(L.Config(grid=256))) == L.OK
+        lib.bwla_workspace_size(L.OP_DOT, 1, L.ACC_PLAIN, 0, 0, 0, 1 << 22, ctypes.byref(b_small))
+        assert lib.bwla_set_config(L.OP_DOT, 1, L.ACC_COMPENSATED, -1, ctypes.byref(L.Config(grid=4096))) == L.OK
+        lib.bwla_workspace_size(L.OP_DOT, 1, L.ACC_PLAIN, 0, 0, 0, 1 << 22, ctypes.byref(b_big))
+        assert b_big.value >= 4096 * 16 > b_small.value
+        # elementwise operations: one entry, whichever mode is named
+        assert lib.bwla_set_config(L.OP_AXPBY, 1, L.ACC_COMPENSATED, -1, ctypes.byref(comp)) == L.OK
+        lib.bwla_get_config(L.OP_AXPBY, 1, L.ACC_COMPENSATED, 0, 1 << 22, ctypes.byref(got))
+        assert got.block == 256 and got.grid != 512   # the plain (default) entry
+        assert lib.bwla_workspace_size(L.OP_DOT, 1, 2, 0, 0, 0, 10, ctypes.byref(b_big)) == L.ERR_UNSUPPORTED
+    finally:
+        for op in range(L.OP_COUNT):
+            lib.bwla_set_config(op, 1, -1, -1, None)
 
 
 def test_load_tuning(L, tmp_path):
     lib = L.lib
     p = tmp_path / "t.txt"
-    p.write_text("# op dtype class block vec unroll grid inc rows split\n"
-                 "1 0 -1 512 2 2 0 0 0 0   # axpby f64\n\n"
-                 "3 1 4 256 4 1 0 0 8 2\n")  # class 4: at least 1 GiB
+    p.write_text("# op dtype acc class block vec unroll grid inc rows split\n"
+                 "1 0 -1 -1 512 2 2 0 0 0 0   # axpby f64\n\n"
+                 "3 1 -1 4 256 4 1 0 0 8 2\n"   # class 4: at least 1 GiB
+                 "2 1 0 -1 1024 4 4 256 0 0 0\n"
+                 "2 1 1 -1 256 4 2 512 1 0 0\n")
     assert lib.bwla_load_tuning(str(p).encode()) == L.OK
     got = L.Config()
-    lib.bwla_get_config(L.OP_AXPBY, 0, 0, 1 << 20, ctypes.byref(got))
+    lib.bwla_get_config(L.OP_AXPBY, 0, 0, 0, 1 << 20, ctypes.byref(got))
     assert (got.block, got.vec, got.unroll) == (512, 2, 2)
-    lib.bwla_get_config(L.OP_GEMV_ROWS, 1, 16384, 16384, ctypes.byref(got))
-    assert (got.rows, got.split) == (8, 2)
-    p.write_text("1 0 -1 500 2 2 0 0 0 0\n")
-    assert lib.bwla_load_tuning(str(p).encode()) == L.ERR_INVALID_ARG
+    for acc in (0, 1):
+        lib.bwla_get_config(L.OP_GEMV_ROWS, 1, acc, 16384, 16384, ctypes.byref(got))
+        assert (got.rows, got.split) == (8, 2)
+    lib.bwla_get_config(L.OP_DOT, 1, 0, 0, 1 << 24, ctypes.byref(got))
+    assert (got.block, got.unroll, got.grid, got.increment) == (1024, 4, 256, 0)
+    lib.bwla_get_config(L.OP_DOT, 1, 1, 0, 1 << 24, ctypes.byref(got))
+    assert (got.block, got.unroll, got.grid, got.increment) == (256, 2, 512, 1)
+    # malformed: a bad block, a bad mode, the old ten-column layout; nothing is installed
+    for text in ("1 0 -1 -1 500 2 2 0 0 0 0\n", "1 0 2 -1 512 2 2 0 0 0 0\n", "1 0 -1 512 2 2 0 0 0 0\n",
+                 "1 0 -1 -1 128 2 2 0 0 0 0\n1 0 -1 -1 500 2 2 0 0 0 0\n"):
+        p.write_text(text)
+        assert lib.bwla_load_tuning(str(p).encode()) == L.ERR_INVALID_ARG, text
+        lib.bwla_get_config(L.OP_AXPBY, 0, 0, 0, 1 << 20, ctypes.byref(got))
+        assert got.block == 512
     assert lib.bwla_load_tuning(b"/nonexistent/file") == L.ERR_INVALID_ARG
     for op in range(L.OP_COUNT):
         for t in range(3):
-            lib.bwla_set_config(op, t, -1, None)
+            lib.bwla_set_config(op, t, -1, -1, None)
 
 
 def test_batch_plan_validation(L):
@@ -190,8 +243,9 @@ def test_host_sizing_never_crashes_on_degenerate_shapes(L):
                             assert lib.bwla_workspace_size(op, t, 0, layout, trans, m, n, ctypes.byref(b)) == L.OK
                 assert lib.bwla_workspace_size(L.OP_DOT, t, 0, 0, 0, 0, n, ctypes.byref(b)) == L.OK
                 for op in range(L.OP_COUNT):
-                    assert lib.bwla_get_config(op, t, m, n, ctypes.byref(c)) == L.OK
-                    assert c.block >= 64 and c.vec >= 1 and c.split >= 1
+                    for acc in (0, 1):
+                        assert lib.bwla_get_config(op, t, acc, m, n, ctypes.byref(c)) == L.OK
+                        assert c.block >= 64 and c.vec >= 1 and c.split >= 1
 
 
 def test_empty_gemv_needs_no_workspace(L):
@@ -314,11 +368,12 @@ def test_rows_block_fits_the_line(L):
     line has packs (rounded up to 64), whatever the table says."""
     lib = L.lib
     got = L.Config()
-    assert lib.bwla_set_config(L.OP_GEMV_ROWS, 1, -1, ctypes.byref(L.Config(block=1024, vec=4, rows=2, split=1))) == L.OK
+    assert lib.bwla_set_config(L.OP_GEMV_ROWS, 1, -1, -1,
+                               ctypes.byref(L.Config(block=1024, vec=4, rows=2, split=1))) == L.OK
     try:
         for n, want in ((2048, 512), (16384, 1024), (100, 64), (4096, 1024), (4100, 1024)):
-            assert lib.bwla_get_config(L.OP_GEMV_ROWS, 1, 16384, n, ctypes.byref(got)) == L.OK
+            assert lib.bwla_get_config(L.OP_GEMV_ROWS, 1, 0, 16384, n, ctypes.byref(got)) == L.OK
             assert got.block == want, (n, got.block)
     finally:
-        lib.bwla_set_config(L.OP_GEMV_ROWS, 1, -1, None)
+        lib.bwla_set_config(L.OP_GEMV_ROWS, 1, -1, -1, None)
 

@@ -38,8 +38,8 @@ def test_gfx950_space_is_valid_for_the_library():
     from paper_1409_0669_amd import tune
     for cfg in tune.vector_space(256)[:200] + tune.rows_space()[:100] + tune.cols_space()[:100]:
         c = L.Config(**cfg)
-        assert L.lib.bwla_set_config(L.OP_DOT, 0, 3, ctypes.byref(c)) == L.OK, cfg
-    L.lib.bwla_set_config(L.OP_DOT, 0, -1, None)
+        assert L.lib.bwla_set_config(L.OP_DOT, 0, -1, 3, ctypes.byref(c)) == L.OK, cfg
+    L.lib.bwla_set_config(L.OP_DOT, 0, -1, -1, None)
     assert len(tune.vector_space(256)) == 5 * 5 * 3 * 2 * 7
 
 
@@ -53,15 +53,16 @@ def test_size_class_agrees_with_library():
     assert [tune.size_class(b) for b in sizes] == [0, 0, 1, 2, 3, 3, 4, 4]
     try:
         for k in range(5):
-            assert L.lib.bwla_set_config(L.OP_COPY, L.F64, k, ctypes.byref(L.Config(block=64 * (k + 1)))) == L.OK
-        assert L.lib.bwla_set_config(L.OP_COPY, L.F64, 5, ctypes.byref(L.Config(block=64))) == L.ERR_INVALID_ARG
+            assert L.lib.bwla_set_config(L.OP_COPY, L.F64, -1, k,
+                                         ctypes.byref(L.Config(block=64 * (k + 1)))) == L.OK
+        assert L.lib.bwla_set_config(L.OP_COPY, L.F64, -1, 5, ctypes.byref(L.Config(block=64))) == L.ERR_INVALID_ARG
         c = L.Config()
         for b in sizes:
             n = b // 16  # a copy streams 2 * 8 bytes per element
-            assert L.lib.bwla_get_config(L.OP_COPY, L.F64, 0, n, ctypes.byref(c)) == L.OK
+            assert L.lib.bwla_get_config(L.OP_COPY, L.F64, 0, 0, n, ctypes.byref(c)) == L.OK
             assert c.block == 64 * (tune.size_class(n * 16) + 1), b
     finally:
-        L.lib.bwla_set_config(L.OP_COPY, L.F64, -1, None)
+        L.lib.bwla_set_config(L.OP_COPY, L.F64, -1, -1, None)
 
 
 def test_write_table_roundtrip(tmp_path):
@@ -70,12 +71,43 @@ def test_write_table_roundtrip(tmp_path):
     from paper_1409_0669_amd import _lib as L
     from paper_1409_0669_amd import tune
     p = str(tmp_path / "t.txt")
-    tune.write_table([(L.OP_AXPBY, torch.float32, 3, dict(block=512, vec=8, unroll=2, grid=2048, increment=1))], p)
+    tune.write_table([(L.OP_AXPBY, torch.float32, None, 3, dict(block=512, vec=8, unroll=2, grid=2048, increment=1)),
+                      (L.OP_DOT, torch.float32, "plain", 3, dict(block=1024, vec=4, unroll=4, grid=256)),
+                      (L.OP_DOT, torch.float32, "compensated", 3, dict(block=256, vec=4, unroll=2, grid=1024))], p)
     assert L.lib.bwla_load_tuning(p.encode()) == L.OK
-    c = L.Config()
-    L.lib.bwla_get_config(L.OP_AXPBY, L.F32, 0, 1 << 26, ctypes.byref(c))
-    assert (c.block, c.vec, c.unroll, c.grid, c.increment) == (512, 8, 2, 2048, 1)
-    L.lib.bwla_set_config(L.OP_AXPBY, L.F32, -1, None)
+    try:
+        c = L.Config()
+        for acc in (L.ACC_PLAIN, L.ACC_COMPENSATED):
+            L.lib.bwla_get_config(L.OP_AXPBY, L.F32, acc, 0, 1 << 26, ctypes.byref(c))
+            assert (c.block, c.vec, c.unroll, c.grid, c.increment) == (512, 8, 2, 2048, 1)
+        L.lib.bwla_get_config(L.OP_DOT, L.F32, L.ACC_PLAIN, 0, 1 << 26, ctypes.byref(c))
+        assert (c.block, c.unroll, c.grid) == (1024, 4, 256)
+        L.lib.bwla_get_config(L.OP_DOT, L.F32, L.ACC_COMPENSATED, 0, 1 << 26, ctypes.byref(c))
+        assert (c.block, c.unroll, c.grid) == (256, 2, 1024)
+    finally:
+        for op in (L.OP_AXPBY, L.OP_DOT):
+            L.lib.bwla_set_config(op, L.F32, -1, -1, None)
+
+
+def test_shipped_table_has_both_accumulation_modes():
+    """The shipped table loads, and every reducing operation it tunes has an
+    entry for each accumulation mode (elementwise operations: one shared)."""
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import tune
+    rows = []
+    for line in open(tune.DEFAULT_TABLE):
+        line = line.split("#")[0].split()
+        if line:
+            assert len(line) == 11, line
+            rows.append(tuple(int(v) for v in line))
+    assert L.lib.bwla_load_tuning(tune.DEFAULT_TABLE.encode()) == L.OK
+    reducing = {L.OP_DOT, L.OP_NRM2, L.OP_CG, L.OP_GEMV_ROWS, L.OP_GEMV_COLS}
+    keys = {(op, t, a, k) for op, t, a, k, *_ in rows}
+    for op, t, a, k, *_ in rows:
+        if op in reducing:
+            assert a in (0, 1) and (op, t, 1 - a, k) in keys, (op, t, a, k)
+        else:
+            assert a == -1, (op, t, a, k)
 
 
 def test_study_analysis_on_synthetic_rates():
@@ -97,6 +129,28 @@ def test_study_analysis_on_synthetic_rates():
     assert set(r["dot_distributions"]) == {"increment", "vec", "block", "grid"}
     md = study.markdown({"device": "synthetic", "cus": 256, "configs": len(space), "sizes": {"2000000": r}})
     assert "Table 2" in md and "Spearman" in md
+
+
+def test_study_tie_band_penalty_range():
+    """Two copy configurations tie (0.5 % apart): one is also the dot's best,
+    the other costs the dot 40 %.  The argmax picks the first, the tie band
+    shows the range 0 .. 40 % over both."""
+    from paper_1409_0669_amd import study, tune
+    space = tune.vector_space(256)[:50]
+    keys = [study._key(c) for c in space]
+    copy = {k: 1000.0 for k in keys}
+    copy[keys[3]], copy[keys[7]] = 5000.0, 4975.0
+    dot = {k: 900.0 for k in keys}
+    dot[keys[3]], dot[keys[7]] = 3000.0, 5000.0
+    rates = {"copy": copy, "axpby": dict(copy), "dot": dot, "nrm2": dict(copy)}
+    r = study.analyse(space, rates)
+    t2 = r["table2"]
+    assert t2["config"] == dict(keys[3]) and t2["tie_configs"] == 2
+    assert t2["dot"]["with_copy_cfg"] == round(3000 / 8000, 3)
+    assert t2["dot"]["tie_penalty_pct"] == {"min": 0.0, "median": 20.0, "max": 40.0}
+    assert t2["axpby"]["tie_penalty_pct"]["max"] == 0.5
+    md = study.markdown({"device": "synthetic", "cus": 256, "configs": len(space), "sizes": {"67108864": r}})
+    assert "0.0 / 20.0 / 40.0 %" in md and "within 2 % of the best copy" in md
 
 
 def test_study_gemv_analysis_on_synthetic_rates():
