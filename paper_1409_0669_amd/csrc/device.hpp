@@ -124,6 +124,14 @@ __device__ __forceinline__ Pack<T, V> load_pack_nt(const T *p)
     return r;
 }
 
+// Ends the load phase of an unrolled trip: no instruction moves across it,
+// so every load issued above is in flight before the arithmetic below starts.
+// Without it the machine scheduler sinks part of a trip's loads into the
+// arithmetic (to shorten register live ranges) and waits on each at once,
+// which cuts the bytes a wave keeps in flight -- on gfx950 down to one or two
+// packs for some compensated instantiations, halving their bandwidth.
+__device__ __forceinline__ void end_of_loads() { __builtin_amdgcn_sched_barrier(0); }
+
 template <typename T, int V>
 __device__ __forceinline__ void store_pack_nt(T *p, const Pack<T, V> &r)
 {

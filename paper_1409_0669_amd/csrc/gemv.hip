@@ -81,6 +81,7 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
             for (int r = 0; r < R; ++r)
                 av[u][r] = load_pack_nt<T, V>(row[r] + (p + (int64_t)u * blockDim.x) * V);
         }
+        end_of_loads();
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     a[u] = load_pack_nt<T, V>(base + (int64_t)(j + u * nw) * ld);
+                end_of_loads();
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const C xl = vs[j + u * nw];

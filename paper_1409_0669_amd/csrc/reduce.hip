@@ -56,6 +56,7 @@ __global__ __launch_bounds__(1024) void k_dot(int64_t n, const T *x, const T *y,
             if constexpr (MODE == kRedDot)
                 vy[u] = load_pack_nt<T, V>(y + (p + u * stride) * V);
         }
+        end_of_loads();
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll

@@ -56,6 +56,7 @@ __global__ __launch_bounds__(1024) void k_copy(int64_t n, const T *y, T *x, int 
 #pragma unroll
         for (int u = 0; u < U; ++u)
             v[u] = load_pack_nt<T, V>(y + (p + u * rg.stride) * V);
+        end_of_loads();
 #pragma unroll
         for (int u = 0; u < U; ++u)
             store_pack_nt<T, V>(x + (p + u * rg.stride) * V, v[u]);
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(1024) void k_scal(int64_t n, compute_t<T> a, const 
 #pragma unroll
         for (int u = 0; u < U; ++u)
             v[u] = load_pack_nt<T, V>(y + (p + u * rg.stride) * V);
+        end_of_loads();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -135,6 +137,7 @@ __global__ __launch_bounds__(1024) void k_axpby(int64_t n, compute_t<T> a, const
             vy[u] = load_pack_nt<T, V>(y + (p + u * rg.stride) * V);
             vz[u] = load_pack_nt<T, V>(z + (p + u * rg.stride) * V);
         }
+        end_of_loads();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             Pack<T, V> o;
@@ -186,6 +189,7 @@ __global__ __launch_bounds__(1024) void k_cg(int64_t n, compute_t<T> a, const co
             vr[u] = load_pack_nt<T, V>(r + o);
             vq[u] = load_pack_nt<T, V>(q + o);
         }
+        end_of_loads();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t o = (i + u * rg.stride) * V;

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(256) void k_strided_elem(int64_t n, compute_t<T> a,
             if constexpr (MODE == kElemAxpby)
                 vz[u] = z[elem_off(i + u * stride, incz, n)];
         }
+        end_of_loads();
 #pragma unroll
         for (int u = 0; u < U; ++u)
             x[elem_off(i + u * stride, incx, n)] = strided_elem<T, MODE>(a, vy[u], b, vz[u]);
@@ -98,6 +99,7 @@ __global__ __launch_bounds__(256) void k_strided_reduce(int64_t n, const T *x, i
             if constexpr (MODE == kRedDot)
                 vy[u] = y[elem_off(i + u * stride, incy, n)];
         }
+        end_of_loads();
 #pragma unroll
         for (int u = 0; u < U; ++u)
             strided_term<T, MODE, COMP>(acc[u], vx[u], MODE == kRedDot ? vy[u] : vx[u]);

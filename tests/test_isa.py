@@ -8,6 +8,11 @@ no numerical test can establish before the kernel runs.
 * The persistent batched kernel must draw work items in a uniform loop: the
   atomic draw sits in the outermost loop's header block with no lane-dependent
   branch around the loop, and the kernel has no barriers at all.
+* Every streaming, reduction and GEMV instantiation that fits its registers
+  keeps (at least three quarters of) the loads of an unrolled trip in flight
+  at once -- the bytes in flight per wave are what the unroll and
+  vector-width axes buy; the machine scheduler may not sink part of them into
+  the arithmetic.
 """
 from __future__ import annotations
 
@@ -15,6 +20,7 @@ import os
 import re
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -92,11 +98,22 @@ def asm_dir(tmp_path_factory):
     return tmp_path_factory.mktemp("asm")
 
 
+# every (source, storage type) the checks below read, compiled in parallel once
+SOURCES = [(src, "float") for src in ("stream", "reduce", "gemv", "ger", "batched", "strided")] + \
+          [(src, t) for src in ("stream", "reduce", "gemv", "batched") for t in ("double", "__bf16")]
+
+
+@pytest.fixture(scope="module")
+def asm(asm_dir):
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
+        texts = list(ex.map(lambda st: compile_asm(st[0], st[1], asm_dir), SOURCES))
+    return dict(zip(SOURCES, texts))
+
+
 @pytest.mark.parametrize("ctype", ["double", "float", "__bf16"])
-def test_batched_kernel_draws_work_in_a_uniform_loop(ctype, asm_dir):
-    asm = compile_asm("batched", ctype, asm_dir)
+def test_batched_kernel_draws_work_in_a_uniform_loop(ctype, asm):
     found = 0
-    for name, lines in functions(asm):
+    for name, lines in functions(asm[("batched", ctype)]):
         if "k_batched" not in name:
             continue
         found += 1
@@ -136,7 +153,76 @@ def test_detector_on_fixture(asm_dir):
 
 
 @pytest.mark.parametrize("src", ["stream", "reduce", "gemv", "ger", "batched", "strided"])
-def test_no_barrier_in_divergent_loop(src, asm_dir):
-    asm = compile_asm(src, "float", asm_dir)
-    hazards = [(name, bad) for name, lines in functions(asm) for bad in [divergent_loops_with_barrier(lines)] if bad]
+def test_no_barrier_in_divergent_loop(src, asm):
+    hazards = [(name, bad) for name, lines in functions(asm[(src, "float")])
+               for bad in [divergent_loops_with_barrier(lines)] if bad]
     assert not hazards, hazards[:3]
+
+
+def loads_in_flight(lines):
+    """Most vector-memory loads outstanding at once inside any basic block
+    (each block starts from none; s_waitcnt vmcnt(k) leaves at most k)."""
+    best = cur = 0
+    for l in lines:
+        t = l.strip()
+        if re.match(r"^(\.LBB\w+:|; %bb\.\d+:)", t):
+            cur = 0
+        elif re.match(r"(global|buffer|flat)_load", t):
+            cur += 1
+            best = max(best, cur)
+        else:
+            m = re.match(r"s_waitcnt\s.*vmcnt\((\d+)\)", t)
+            if m:
+                cur = min(cur, int(m.group(1)))
+    return best
+
+
+KERNEL = re.compile(r"_ZN4bwla\d+(k_\w+?)I(?:d|f|DF16b)((?:L[ib]\d+E)+)E")
+ELEM = {"double": 8, "float": 4, "__bf16": 2}
+
+
+def trip_loads(kernel, args, es):
+    """Loads one unrolled trip issues, from the template arguments (a pack of
+    V elements is max(1, V * es / 16) 16-byte loads)."""
+    lp = lambda v: max(1, v * es // 16)
+    if kernel in ("k_copy", "k_scal"):
+        return args[1] * lp(args[0])
+    if kernel == "k_axpby":
+        return 2 * args[1] * lp(args[0])
+    if kernel == "k_cg":
+        return 4 * args[1] * lp(args[0])
+    if kernel == "k_dot":          # <V, U, COMP, MODE>: two streams for the inner product
+        return args[1] * lp(args[0]) * (2 if args[3] == 0 else 1)
+    if kernel == "k_gemv_rows":    # <V, R, U, COMP>: R lines of A and the x pack per trip
+        return args[2] * (args[1] + 1) * lp(args[0])
+    if kernel == "k_gemv_cols":    # <V, U, COMP>: U lines
+        return args[1] * lp(args[0])
+    return None
+
+
+@pytest.mark.parametrize("src", ["stream", "reduce", "gemv"])
+@pytest.mark.parametrize("ctype", ["double", "float", "__bf16"])
+def test_unrolled_trips_keep_every_load_in_flight(src, ctype, asm):
+    text = asm[(src, ctype)]
+    spills = {m.group(1): int(re.search(r"\.vgpr_spill_count:\s+(\d+)", m.group(2)).group(1))
+              for m in re.finditer(r"\.name:\s+(\S+)\n(.*?)(?=\n  - \.|\Z)", text, re.S)
+              if re.search(r"\.vgpr_spill_count:", m.group(2))}
+    checked, short = 0, []
+    for name, lines in functions(text):
+        m = KERNEL.match(name)
+        if not m or spills.get(name, 0):
+            continue  # not an unrolled streaming kernel, or it cannot hold a trip in registers
+        args = [int(v) for v in re.findall(r"L[ib](\d+)E", m.group(2))]
+        want = trip_loads(m.group(1), args, ELEM[ctype])
+        if want is None:
+            continue
+        checked += 1
+        got = loads_in_flight(lines)
+        # at least three quarters: the instruction selector may still place a
+        # conversion that consumes the first loads ahead of the last ones
+        # (bf16 pairs of the four-stream update), which costs little; a trip
+        # cut to a few loads in flight costs half the bandwidth
+        if 4 * got < 3 * want:
+            short.append((m.group(1), args, got, want))
+    assert checked >= 20, checked
+    assert not short, short[:5]
