@@ -88,8 +88,9 @@ typedef enum {
  * out.  A zero field means "library default".  Which fields an op uses:
  *   COPY, AXPBY, DOT, NRM2, CG: block, vec, unroll, grid, increment
  *   GEMV_ROWS:        block, vec, rows (lines per block), unroll (packs of each
- *                     line in flight: 1 or 2), split (blocks along a line)
- *   GEMV_COLS:        block, vec, unroll (lines in flight), split (blocks across lines)
+ *                     line in flight: 1 or 2), split (blocks along a line), grid
+ *   GEMV_COLS:        block, vec, unroll (lines in flight), split (blocks across
+ *                     lines), grid
  *   GER:              block, vec, rows
  * block:  threads per work-group, a multiple of 64 in [64, 1024]
  * vec:    consecutive elements per thread per access: 1, 2, 4, 8 or 16 (the
@@ -99,10 +100,16 @@ typedef enum {
  *         or 8 (8 for DOT, NRM2 and GEMV_COLS; the streaming operations take 4)
  * GEMV_ROWS work-groups are never larger than the packs of one slice of a
  * line (rounded up to 64 threads), whatever the table says.
- * grid:   number of work-groups (streaming and reductions)
+ * grid:   number of work-groups (streaming and reductions).  For GEMV_ROWS
+ *         and GEMV_COLS with split 0, a nonzero grid is the number of
+ *         work-groups the split aims for on every shape: split =
+ *         ceil(grid / output tiles), so an entry tuned on one shape of a
+ *         size class keeps its work-group count on other aspect ratios.
+ *         bwla_get_config reports in grid the work-groups a GEMV launches.
  * rows:   1, 2, 4 or 8
  * split:  >= 1; values above 1 make several work-groups share one output
- *         tile, combining their float64 partials in a fixed order. */
+ *         tile, combining their float64 partials in a fixed order.  0: from
+ *         grid, or (grid 0) a library heuristic that follows the shape. */
 typedef struct {
     int32_t block, vec, unroll, grid, increment, rows, split;
 } bwla_config;

@@ -192,12 +192,15 @@ Cfg resolve_rows(int t, int acc, int64_t L, int64_t K, const void *A, int64_t ld
     c.block = u.block ? u.block : 1024;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A, v}, ld);
     c.unroll = u.unroll == 2 ? 2 : 1; // packs of each line in flight per thread: 1 or 2
-    c.grid = 0;
     c.inc = 0;
     c.rows = u.rows ? u.rows : 2;
     const int64_t groups = std::max<int64_t>(1, ceil_div(L, c.rows));
     int64_t split = u.split;
-    if (!split) {
+    if (!split && u.grid) {
+        // a work-group count tuned on one shape of the size class: keep that
+        // count on every aspect ratio of the class
+        split = ceil_div(u.grid, groups);
+    } else if (!split) {
         // enough work-groups for every CU to hold two, each slice at least
         // two block-widths of packs long
         const int64_t target = (int64_t)device_cus() * 2;
@@ -208,6 +211,7 @@ Cfg resolve_rows(int t, int acc, int64_t L, int64_t K, const void *A, int64_t ld
     split = std::max<int64_t>(1, std::min<int64_t>(split, std::max<int64_t>(1, K)));
     split = std::min<int64_t>(split, (int64_t)(0x7fffffff / std::max<int64_t>(1, groups)));
     c.split = (int)split;
+    c.grid = (int)std::min<int64_t>(groups * split, 0x7fffffff); // reported only: work-groups launched
     // No more threads than the packs of a slice: a table entry tuned on long
     // lines would leave most of a work-group idle on short ones.
     const int64_t per_slice = ceil_div(std::max<int64_t>(1, K / c.vec), split);
@@ -224,21 +228,25 @@ Cfg resolve_cols(int t, int acc, int64_t L, int64_t K, const void *A, int64_t ld
     c.block = u.block ? u.block : 512;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A}, ld);
     c.unroll = u.unroll ? u.unroll : 4; // lines in flight per wave: 1, 2, 4 or 8
-    c.grid = 0;
     c.inc = 0;
     c.rows = 1;
     const int64_t tiles = std::max<int64_t>(1, ceil_div(K, 64 * (int64_t)c.vec));
+    const int64_t waves = c.block / 64;
     int64_t split = u.split;
-    if (!split) {
+    if (!split && u.grid) {
+        // a work-group count tuned on one shape of the size class (see the rows kernel)
+        split = ceil_div(u.grid, tiles);
+        split = std::min<int64_t>(split, std::max<int64_t>(1, L / waves)); // every wave keeps a line
+    } else if (!split) {
         // about one work-group per CU, each wave with at least 16 lines
         const int64_t target = (int64_t)device_cus();
-        const int64_t waves = c.block / 64;
         split = tiles >= target ? 1 : ceil_div(target, tiles);
         split = std::min<int64_t>(split, std::max<int64_t>(1, L / (waves * 16)));
     }
     split = std::max<int64_t>(1, std::min<int64_t>(split, std::max<int64_t>(1, L)));
     split = std::min<int64_t>(split, (int64_t)(0x7fffffff / std::max<int64_t>(1, tiles)));
     c.split = (int)split;
+    c.grid = (int)std::min<int64_t>(tiles * split, 0x7fffffff); // reported only: work-groups launched
     return c;
 }
 

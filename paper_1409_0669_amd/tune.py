@@ -268,6 +268,23 @@ def _ger_candidates(dtype, quick):
             for v in (max(1, native // 2), native, min(16, 2 * native)) for r in (1, 2, 4, 8)]
 
 
+def as_group_count(w: Workload, cfg: dict) -> dict:
+    """A GEMV entry with an explicit split, rewritten as the work-group count
+    it launches on the tuning shape (split 0, grid = that count): the library
+    then picks the split that keeps this count on every shape of the size
+    class, where a fixed split would leave a tall or wide shape with a few
+    output tiles running on part of the GPU."""
+    if not cfg.get("split"):
+        return cfg
+    ops.set_config(w.table_op, w.dtype, w.cls, acc=w.table_acc, **cfg)
+    try:
+        m, n = (w.m, w.n) if w.layout == "row" else (w.n, w.m)  # lines, line length of the kernel's view
+        groups = ops.get_config(w.table_op, w.dtype, m, n, acc=w.table_acc)["grid"]
+    finally:
+        ops.set_config(w.table_op, w.dtype, w.cls, acc=w.table_acc)
+    return dict(cfg, split=0, grid=groups)
+
+
 def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
     """Sweep every operation, storage type, accumulation mode (for the
     reducing operations) and size class; return the table entries and a
@@ -314,7 +331,7 @@ def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
                     w = Workload("gemv", dt, n=n, m=m, layout=layout, acc=acc)
                     default_ms = time_ms(w.run, reps=10)
                     res = sweep(w, cands_g, reps=6, refine=refine)
-                    entries.append((w.table_op, dt, acc, w.cls, res[0][0]))
+                    entries.append((w.table_op, dt, acc, w.cls, as_group_count(w, res[0][0])))
                     record(w, res, default_ms, dn=dn, m=m, n=n)
                     del w
         for (m, n) in ((4096, 4096), (16384, 16384)):

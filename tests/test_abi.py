@@ -363,6 +363,35 @@ def test_gemv_ex_validation_and_workspace(L):
     assert lib.bwla_gemv_ex_workspace_size(0, 0, 0, 0, 0, 5, ctypes.byref(b)) == L.OK and b.value == 0
 
 
+def test_gemv_split_keeps_a_tuned_work_group_count(L):
+    """With split 0 and a nonzero grid, a GEMV entry keeps its work-group
+    count on every aspect ratio: split = ceil(grid / output tiles).  An
+    explicit split stays fixed."""
+    lib = L.lib
+    got = L.Config()
+    try:
+        assert lib.bwla_set_config(L.OP_GEMV_COLS, 1, -1, -1,
+                                   ctypes.byref(L.Config(block=512, vec=2, unroll=8, grid=256))) == L.OK
+        # (lines, line length): tiles of 64 * vec = 128 outputs
+        for lines, length, split in ((4096, 4096, 8), (16384, 2048, 16), (2048, 16384, 2), (40, 4096, 5)):
+            assert lib.bwla_get_config(L.OP_GEMV_COLS, 1, 0, lines, length, ctypes.byref(got)) == L.OK
+            assert got.split == split, (lines, length, got.split)
+            assert got.grid == -(-length // 128) * split
+        assert lib.bwla_set_config(L.OP_GEMV_ROWS, 1, -1, -1,
+                                   ctypes.byref(L.Config(block=512, vec=4, rows=8, grid=512))) == L.OK
+        for lines, length, split in ((4096, 4096, 1), (2048, 16384, 2), (16384, 2048, 1), (512, 16384, 8)):
+            assert lib.bwla_get_config(L.OP_GEMV_ROWS, 1, 0, lines, length, ctypes.byref(got)) == L.OK
+            assert got.split == split, (lines, length, got.split)
+            assert got.grid == -(-lines // 8) * split
+        assert lib.bwla_set_config(L.OP_GEMV_ROWS, 1, -1, -1,
+                                   ctypes.byref(L.Config(block=512, vec=4, rows=8, split=3, grid=512))) == L.OK
+        lib.bwla_get_config(L.OP_GEMV_ROWS, 1, 0, 2048, 16384, ctypes.byref(got))
+        assert got.split == 3
+    finally:
+        for op in (L.OP_GEMV_ROWS, L.OP_GEMV_COLS):
+            lib.bwla_set_config(op, 1, -1, -1, None)
+
+
 def test_rows_block_fits_the_line(L):
     """A rows-GEMV work-group never holds more threads than one slice of a
     line has packs (rounded up to 64), whatever the table says."""
