@@ -248,41 +248,71 @@ def _vector_candidates(dtype, cus, quick, reduction=False):
             for b in blocks for v in vecs for u in unrolls for i in (0, 1) for g in grids]
 
 
-def _rows_candidates(dtype, quick):
-    native = 16 // torch.tensor([], dtype=dtype).element_size()
-    vecs = (native,) if quick else (max(1, native // 2), native)
-    return [dict(block=b, vec=v, rows=r, unroll=u, split=s) for b in (256, 512, 1024) for v in vecs
-            for r in (1, 2, 4, 8) for u in (1, 2) for s in (0, 1, 2, 4)]
+# GEMV candidates name a work-group count (per CU; 0 = the library's
+# heuristic) rather than a split: the library turns it into the split of each
+# shape, so one candidate means the same on a square, a tall and a wide matrix
+GEMV_GROUPS_PER_CU = (0, 1, 2, 4, 8, 16, 32, 64)
 
 
-def _cols_candidates(dtype, quick):
+def _rows_candidates(dtype, quick, cus=256):
     native = 16 // torch.tensor([], dtype=dtype).element_size()
     vecs = (native,) if quick else (max(1, native // 2), native)
-    return [dict(block=b, vec=v, unroll=u, split=s) for b in (256, 512, 1024) for v in vecs
-            for u in (2, 4, 8) for s in (0, 1, 2, 4, 8, 16)]
+    return [dict(block=b, vec=v, rows=r, unroll=u, split=0, grid=g * cus) for b in (256, 512, 1024) for v in vecs
+            for r in (1, 2, 4, 8) for u in (1, 2) for g in GEMV_GROUPS_PER_CU]
+
+
+def _cols_candidates(dtype, quick, cus=256):
+    native = 16 // torch.tensor([], dtype=dtype).element_size()
+    vecs = (native,) if quick else (max(1, native // 2), native)
+    return [dict(block=b, vec=v, unroll=u, split=0, grid=g * cus) for b in (256, 512, 1024) for v in vecs
+            for u in (2, 4, 8) for g in GEMV_GROUPS_PER_CU]
+
+
+# GEMV shapes tuned; each size class is tuned on every shape that falls in it
+# (the square matrices of the paper-scale workload and the tall and wide
+# shards of the differentiation workload)
+GEMV_SHAPES = ((1024, 1024), (4096, 4096), (16384, 2048), (2048, 16384), (8192, 8192), (16384, 16384))
+
+
+def multi_shape_pick(workloads, candidates, reps=6, refine=6, refine_rounds=5, log=None):
+    """The candidate with the best geometric mean of GB/s over several
+    workloads (shapes of one size class, all with the same table entry).
+    Every candidate is timed once per workload; the `refine` best by that
+    score are timed again round-robin over `refine_rounds` rounds and ranked
+    by the geometric mean of their medians.  Returns (best config, score in
+    GB/s, {workload index: GB/s of the best})."""
+    keyf = lambda c: json.dumps(c, sort_keys=True)
+    per = []
+    for w in workloads:
+        per.append({keyf(c): (c, g) for c, _, g in sweep(w, candidates, reps=reps, log=log)})
+    common = [k for k in per[0] if all(k in p for p in per[1:])]
+
+    def gmean(vals):
+        return float(statistics.geometric_mean(vals))
+
+    ranked = sorted(common, key=lambda k: -gmean([p[k][1] for p in per]))
+    top = ranked[:max(1, refine)]
+    if refine > 1 and len(top) > 1:
+        runs = {k: [[] for _ in workloads] for k in top}
+        for _ in range(refine_rounds):
+            for k in top:
+                for i, w in enumerate(workloads):
+                    ops.set_config(w.table_op, w.dtype, w.cls, acc=w.table_acc, **per[0][k][0])
+                    runs[k][i].append(time_ms(w.run, reps=reps))
+        w0 = workloads[0]
+        ops.set_config(w0.table_op, w0.dtype, w0.cls, acc=w0.table_acc)
+        rate = {k: [w.bytes / (statistics.median(runs[k][i]) * 1e-3) / 1e9 for i, w in enumerate(workloads)]
+                for k in top}
+        best = max(top, key=lambda k: gmean(rate[k]))
+        return per[0][best][0], gmean(rate[best]), dict(enumerate(rate[best]))
+    best = ranked[0]
+    return per[0][best][0], gmean([p[best][1] for p in per]), {i: p[best][1] for i, p in enumerate(per)}
 
 
 def _ger_candidates(dtype, quick):
     native = 16 // torch.tensor([], dtype=dtype).element_size()
     return [dict(block=b, vec=v, rows=r) for b in (128, 256, 512, 1024)
             for v in (max(1, native // 2), native, min(16, 2 * native)) for r in (1, 2, 4, 8)]
-
-
-def as_group_count(w: Workload, cfg: dict) -> dict:
-    """A GEMV entry with an explicit split, rewritten as the work-group count
-    it launches on the tuning shape (split 0, grid = that count): the library
-    then picks the split that keeps this count on every shape of the size
-    class, where a fixed split would leave a tall or wide shape with a few
-    output tiles running on part of the GPU."""
-    if not cfg.get("split"):
-        return cfg
-    ops.set_config(w.table_op, w.dtype, w.cls, acc=w.table_acc, **cfg)
-    try:
-        m, n = (w.m, w.n) if w.layout == "row" else (w.n, w.m)  # lines, line length of the kernel's view
-        groups = ops.get_config(w.table_op, w.dtype, m, n, acc=w.table_acc)["grid"]
-    finally:
-        ops.set_config(w.table_op, w.dtype, w.cls, acc=w.table_acc)
-    return dict(cfg, split=0, grid=groups)
 
 
 def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
@@ -325,15 +355,25 @@ def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
                 for cls, cfg in best_for_class.items():
                     entries.append((Workload_table_op(op), dt, acc if op in REDUCING else None, cls, cfg))
         report["copy_proxy"][dn] = copy_proxy(proxy_in)
-        for (m, n) in ((1024, 1024), (4096, 4096), (8192, 8192), (16384, 16384)):
-            for layout, cands_g in (("row", _rows_candidates(dt, quick)), ("col", _cols_candidates(dt, quick))):
-                for acc in ("plain", "compensated"):
-                    w = Workload("gemv", dt, n=n, m=m, layout=layout, acc=acc)
-                    default_ms = time_ms(w.run, reps=10)
-                    res = sweep(w, cands_g, reps=6, refine=refine)
-                    entries.append((w.table_op, dt, acc, w.cls, as_group_count(w, res[0][0])))
-                    record(w, res, default_ms, dn=dn, m=m, n=n)
-                    del w
+        es = torch.tensor([], dtype=dt).element_size()
+        by_class = {}
+        for (m, n) in GEMV_SHAPES:
+            by_class.setdefault(size_class((m * n + m + n) * es), []).append((m, n))
+        for layout, cands_g in (("row", _rows_candidates(dt, quick, cus)), ("col", _cols_candidates(dt, quick, cus))):
+            for acc in ("plain", "compensated"):
+                for cls, shapes in sorted(by_class.items()):
+                    ws = [Workload("gemv", dt, n=n, m=m, layout=layout, acc=acc) for (m, n) in shapes]
+                    default = [w.bytes / (time_ms(w.run, reps=10) * 1e-3) / 1e9 for w in ws]
+                    cfg, score, rates = multi_shape_pick(ws, cands_g, refine=refine)
+                    entries.append((ws[0].table_op, dt, acc, cls, cfg))
+                    rec = {"op": "gemv_" + layout, "dtype": dn, "acc": acc, "class": cls, "shapes": shapes,
+                           "best": cfg, "best_gbs_per_shape": [round(rates[i], 1) for i in range(len(ws))],
+                           "best_gbs_geomean": round(score, 1), "default_gbs_per_shape": [round(d, 1) for d in default]}
+                    report["results"].append(rec)
+                    log("gemv_%-4s %-4s %-11s class %d %-40s best %s GB/s default %s GB/s %s" % (
+                        layout, dn, acc, cls, " ".join("%dx%d" % sh for sh in shapes), rec["best_gbs_per_shape"],
+                        rec["default_gbs_per_shape"], cfg))
+                    del ws
         for (m, n) in ((4096, 4096), (16384, 16384)):
             w = Workload("ger", dt, n=n, m=m)
             default_ms = time_ms(w.run, reps=10)

@@ -171,3 +171,39 @@ def test_study_gemv_analysis_on_synthetic_rates():
          "copy_vs_ops": {}, "dot_distributions": {}, "gemv": dict(g, m=2048)}
     md = study.markdown({"device": "synthetic", "cus": 256, "configs": 1, "sizes": {"2000000": r}})
     assert "one row per work-group" in md and "2048 x 2048" in md
+
+
+def test_multi_shape_pick_ranks_by_geometric_mean(monkeypatch):
+    """A size class tuned on several shapes keeps the candidate whose
+    geometric mean over the shapes is best, not the winner of one shape; the
+    refinement re-times the leaders and can overturn the first ranking."""
+    import torch
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import tune
+
+    class FakeW:
+        def __init__(self, name):
+            self.name, self.table_op, self.dtype, self.cls, self.table_acc = name, L.OP_GEMV_ROWS, torch.float32, 2, "plain"
+            self.bytes = 1e9
+
+        def run(self):
+            pass
+
+    cands = [dict(block=256, grid=g) for g in (256, 512, 1024)]
+    # first timing: the square shape loves grid 256, the tall one hates it
+    first = {"square": {256: 7000.0, 512: 6000.0, 1024: 5000.0},
+             "tall": {256: 1000.0, 512: 4000.0, 1024: 4500.0}}
+    monkeypatch.setattr(tune, "sweep", lambda w, c, reps=6, log=None: sorted(
+        ((cfg, 1.0, first[w.name][cfg["grid"]]) for cfg in c), key=lambda r: -r[2]))
+    ws = [FakeW("square"), FakeW("tall")]
+    cfg, score, rates = tune.multi_shape_pick(ws, cands, refine=0)
+    # geometric means: 256 -> 2646, 512 -> 4899, 1024 -> 4743 (the square's winner comes last)
+    assert cfg["grid"] == 512
+    assert abs(score - (6000.0 * 4000.0) ** 0.5) < 1e-6 and rates == {0: 6000.0, 1: 4000.0}
+    # with refinement the re-timed medians decide: make grid 1024 the clear winner
+    current = {}
+    monkeypatch.setattr(tune.ops, "set_config", lambda *a, **k: current.update(k))
+    slow = {256: 2.0, 512: 0.5, 1024: 0.2}  # ms for 1 GB
+    monkeypatch.setattr(tune, "time_ms", lambda fn, reps=10, warmup=2: slow[current["grid"]])
+    cfg, score, rates = tune.multi_shape_pick(ws, cands, refine=3, refine_rounds=2)
+    assert cfg["grid"] == 1024 and abs(score - 5000.0) < 1e-6 and len(rates) == 2
