@@ -95,16 +95,20 @@ def test_gemv_empty():
     assert ops.gemv(A, torch.zeros(6, dtype=torch.float32, device="cuda")).numel() == 0
 
 
+# the last two of each list give a work-group count instead of a split: the
+# split then follows each shape (ceil(grid / output tiles)), ragged counts
 ROWS_CFG = [dict(block=64, vec=1, rows=1, split=1), dict(block=128, vec=2, rows=2, split=3, unroll=2),
             dict(block=256, vec=4, rows=8, split=1, unroll=2), dict(block=1024, vec=16, rows=4, split=2),
-            dict(block=512, vec=8, rows=1, split=7, unroll=2)]
+            dict(block=512, vec=8, rows=1, split=7, unroll=2),
+            dict(block=256, vec=4, rows=4, split=0, grid=1000, unroll=2), dict(block=128, vec=2, rows=8, grid=37)]
 COLS_CFG = [dict(block=64, vec=1, unroll=1, split=1), dict(block=128, vec=2, unroll=2, split=3),
             dict(block=256, vec=4, unroll=4, split=1), dict(block=1024, vec=16, unroll=4, split=2),
-            dict(block=512, vec=8, unroll=1, split=9)]
+            dict(block=512, vec=8, unroll=1, split=9),
+            dict(block=256, vec=2, unroll=8, split=0, grid=700), dict(block=512, vec=4, unroll=2, grid=33)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("cfg", range(5))
+@pytest.mark.parametrize("cfg", range(len(ROWS_CFG)))
 def test_gemv_configs(dtype, cfg):
     from paper_1409_0669_amd import _lib as L
     from paper_1409_0669_amd import ops
@@ -119,6 +123,23 @@ def test_gemv_configs(dtype, cfg):
                     y = ops.gemv(A, x, trans=bool(trans), acc=acc)
                     ref, scale = _ref(A64, x64, trans)
                     check_vector(host(y), ref, scale, TOL[dtype], "%s %s %s" % (cfg, layout, trans))
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+@pytest.mark.parametrize("shape", [(4096, 4096), (16384, 2048), (2048, 16384)])
+def test_gemv_shipped_table_on_differentiation_shapes(acc, shape):
+    """The shipped table's GEMV entries (work-group counts that the split
+    follows on each shape) on the f32 shapes of the differentiation workload:
+    y = A x and dx = A^T ybar against the oracle, every output."""
+    from paper_1409_0669_amd import ops
+    assert ops.load_default_tuning()
+    m, n = shape
+    A, A64 = mat(m, n, "f32", 28, layout="row")
+    for trans in (0, 1):
+        x, x64 = vec(m if trans else n, "f32", 29)
+        y = ops.gemv(A, x, trans=bool(trans), acc=acc)
+        ref, scale = _ref(A64, x64, trans)
+        check_vector(host(y), ref, scale, TOL["f32"], "%s %s trans=%d" % (acc, shape, trans))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
