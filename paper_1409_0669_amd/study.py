@@ -26,6 +26,11 @@ analogue runs the paper's mapping -- one work-group per row -- with the
 copy's best work-group size and vector width, against the GEMV's own best;
 the best of the one-row-per-work-group configurations is reported as well.
 
+Every configuration is timed as the tuner times it (``tune.time_ms``: the
+median over repetitions of a HIP-event interval around four calls launched
+back to back, divided by four), so a rate is the one the operation sustains in
+a sequence of operations rather than one call's on an idle GPU.
+
 Run on the GPU: ``python -m paper_1409_0669_amd.study --json OUT.json --md OUT.md``.
 """
 from __future__ import annotations

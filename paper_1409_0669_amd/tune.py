@@ -85,19 +85,28 @@ def size_class(nbytes: float) -> int:
 
 
 # ---- timing ----------------------------------------------------------------
-def time_ms(fn, reps: int = 10, warmup: int = 2) -> float:
-    """Median duration of fn() over `reps` runs, each bracketed by HIP events
-    recorded on the current stream (the stream the library launches on)."""
+PIPELINE = 4  # calls per timed interval
+
+
+def time_ms(fn, reps: int = 10, warmup: int = 2, batch: int = PIPELINE) -> float:
+    """Median duration of one fn() call: `reps` intervals, each bracketed by
+    HIP events recorded on the current stream (the stream the library
+    launches on) around `batch` calls launched back to back, divided by
+    `batch`.  Back-to-back calls overlap each launch with the work before it,
+    as a sequence of operations does; a call timed alone also holds the
+    dispatch latency of an idle GPU (about 10 us), the same for every
+    configuration."""
     for _ in range(warmup):
         fn()
     times = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        fn()
+        for _ in range(batch):
+            fn()
         e1.record()
         e1.synchronize()
-        times.append(e0.elapsed_time(e1))
+        times.append(e0.elapsed_time(e1) / batch)
     return statistics.median(times)
 
 
