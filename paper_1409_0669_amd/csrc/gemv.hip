@@ -256,6 +256,8 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
 // partials in slice order.  Consecutive outputs read consecutive partials.
 // With w (same element type as out), the work-group also reduces w_o * y_o
 // over its outputs into dparts[blockIdx.x].
+constexpr int kCombineBatch = 8;
+
 template <bool COMP>
 __global__ __launch_bounds__(256) void k_combine_lines(const DD *partials, int64_t outputs, int64_t G,
                                                        int64_t split, void *out, int out_f64,
@@ -268,8 +270,21 @@ __global__ __launch_bounds__(256) void k_combine_lines(const DD *partials, int64
     if (live) {
         const int64_t g = o / G, r = o - g * G;
         const DD *p = partials + g * split * G + r;
+        // slice order as written, with kCombineBatch partials in flight at a
+        // time (one at a time, a split of 128 cost 32 us of load latency)
         DD t = p[0];
-        for (int64_t q = 1; q < split; ++q)
+        int64_t q = 1;
+        for (; q + kCombineBatch <= split; q += kCombineBatch) {
+            DD v[kCombineBatch];
+#pragma unroll
+            for (int b = 0; b < kCombineBatch; ++b)
+                v[b] = p[(q + b) * G];
+            end_of_loads();
+#pragma unroll
+            for (int b = 0; b < kCombineBatch; ++b)
+                t = combine<COMP>(t, v[b]);
+        }
+        for (; q < split; ++q)
             t = combine<COMP>(t, p[q * G]);
         y = t.hi + t.lo;
         store_out(out, o, out_f64, y);

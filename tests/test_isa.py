@@ -177,7 +177,7 @@ def loads_in_flight(lines):
     return best
 
 
-KERNEL = re.compile(r"_ZN4bwla\d+(k_\w+?)I(?:d|f|DF16b)((?:L[ib]\d+E)+)E")
+KERNEL = re.compile(r"_ZN4bwla\d+(k_\w+?)I(?:d|f|DF16b)?((?:L[ib]\d+E)+)E")
 ELEM = {"double": 8, "float": 4, "__bf16": 2}
 
 
@@ -197,6 +197,8 @@ def trip_loads(kernel, args, es):
         return args[2] * (args[1] + 1) * lp(args[0])
     if kernel == "k_gemv_cols":    # <V, U, COMP>: U lines
         return args[1] * lp(args[0])
+    if kernel == "k_combine_lines":  # <COMP>: a batch of eight 16-byte partials
+        return 8
     return None
 
 
