@@ -103,14 +103,30 @@ __global__ void k_fill_zero(void *out, int64_t count, int out_f64)
 }
 
 // Stage 2 of the scalar reductions: one work-group sums the partials, each
-// thread a fixed strided subset, then the work-group tree.
+// thread a fixed strided subset in index order with kScalarBatch loads in
+// flight, then the work-group tree.  Many partials (grids of one work-group
+// per few KiB) get 1024 threads instead of 256.
+constexpr int kScalarBatch = 8;
+
 template <bool COMP>
-__global__ __launch_bounds__(256) void k_combine_scalar(const DD *partials, int64_t count, void *out,
-                                                        int out_f64, int do_sqrt)
+__global__ __launch_bounds__(1024) void k_combine_scalar(const DD *partials, int64_t count, void *out,
+                                                         int out_f64, int do_sqrt)
 {
     __shared__ DD lds[16];
     DD t = {0.0, 0.0};
-    for (int64_t i = threadIdx.x; i < count; i += blockDim.x)
+    const int64_t step = blockDim.x;
+    int64_t i = threadIdx.x;
+    for (; i + (kScalarBatch - 1) * step < count; i += kScalarBatch * step) {
+        DD v[kScalarBatch];
+#pragma unroll
+        for (int b = 0; b < kScalarBatch; ++b)
+            v[b] = partials[i + b * step];
+        end_of_loads();
+#pragma unroll
+        for (int b = 0; b < kScalarBatch; ++b)
+            t = combine<COMP>(t, v[b]);
+    }
+    for (; i < count; i += step)
         t = combine<COMP>(t, partials[i]);
     t = block_sum<COMP>(t, lds);
     if (threadIdx.x == 0) {
@@ -174,7 +190,8 @@ hipError_t launch_combine_scalar(const void *partials, int64_t count, bool comp,
                                  int out_f64, void *out, hipStream_t s)
 {
     return with_bool(comp, [&](auto CP) {
-        hipLaunchKernelGGL((k_combine_scalar<CP.value>), dim3(1), dim3(256), 0, s, (const DD *)partials,
+        const int threads = count > 8 * 256 ? 1024 : 256;
+        hipLaunchKernelGGL((k_combine_scalar<CP.value>), dim3(1), dim3(threads), 0, s, (const DD *)partials,
                            count, out, out_f64, (int)do_sqrt);
         return hipGetLastError();
     });
