@@ -88,6 +88,10 @@ CONFIGS = [
     dict(block=512, vec=16, unroll=2, grid=300),
     dict(block=256, vec=4, unroll=8, grid=2048),
     dict(block=1024, vec=2, unroll=8, grid=0, increment=1),
+    # more than 2048 partials: the second stage runs 1024 threads, with
+    # eight-load batches (20000 partials) or the remainder loop only (one pass)
+    dict(block=64, vec=1, unroll=1, grid=20000),
+    dict(block=128, vec=1, unroll=1, grid=0),
 ]
 
 
