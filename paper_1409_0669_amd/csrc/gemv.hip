@@ -66,6 +66,12 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
     const int64_t per = (kpack + split - 1) / split;
     const int64_t pb = (int64_t)s * per;
     const int64_t pe = pb + per < kpack ? pb + per : kpack;
+    // the dot epilogue's weight of this thread's line, fetched before the
+    // main loop: read at the end it would be one more memory latency in
+    // every work-group's tail
+    C wl = C(0);
+    if (w != nullptr && split == 1 && (int)threadIdx.x < nr)
+        wl = widen(w[l0 + threadIdx.x]);
 
     // U trips of the pack loop per iteration, all loads first: R * U packs of
     // A in flight per thread.  Each row's sum still takes the packs in the
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
     if (w != nullptr && split == 1 && wave == 0) { // the whole first wave
         DD d = {0.0, 0.0};
         if ((int)threadIdx.x < nr)
-            d = epilogue_term<C, COMP>(widen(w[l0 + threadIdx.x]), (C)(t.hi + t.lo));
+            d = epilogue_term<C, COMP>(wl, (C)(t.hi + t.lo));
         d = wave_sum<COMP>(d);
         if (lane == 0)
             dparts[group] = d;

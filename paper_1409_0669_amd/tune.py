@@ -16,6 +16,13 @@ flight), times every candidate with HIP events on the current stream, writes a
 tuning table the C library loads (``bwla_load_tuning``), and reports the copy
 proxy: each operation run with the copy's best configuration against its own
 best (the Table 2 analogue).
+
+The table has one entry per (operation, storage type, accumulation mode, size
+class).  The reducing operations are tuned once per accumulation mode
+(compensated arithmetic wants more waves in flight than plain); a GEMV size
+class is tuned on every workload shape that falls in it and keeps the
+candidate with the best geometric mean, its work-group count written so that
+the library derives each shape's split from it.
 """
 from __future__ import annotations
 
