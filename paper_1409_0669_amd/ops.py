@@ -76,13 +76,14 @@ _ws_lock = threading.Lock()
 _ws: dict = {}
 
 
-def workspace(nbytes: int, device: torch.device) -> torch.Tensor | None:
-    """A workspace of at least ``nbytes`` for the current stream, reused by
-    every call on that stream and reallocated only when it must grow.  Grow it
-    before any graph capture with :func:`reserve_workspace`."""
+def workspace(nbytes: int, device: torch.device, stream: int | None = None) -> torch.Tensor | None:
+    """A workspace of at least ``nbytes`` for the current stream (or the
+    stream handle given), reused by every call on that stream and reallocated
+    only when it must grow.  Grow it before any graph capture with
+    :func:`reserve_workspace`."""
     if nbytes == 0:
         return None
-    key = (device.index, torch.cuda.current_stream(device).cuda_stream)
+    key = (device.index, torch.cuda.current_stream(device).cuda_stream if stream is None else stream)
     with _ws_lock:
         buf = _ws.get(key)
         if buf is None or buf.numel() < nbytes:
@@ -101,11 +102,39 @@ def _ws_ptr(buf):
     return (ctypes.c_void_p(buf.data_ptr()), buf.numel()) if buf is not None else (None, 0)
 
 
+# Workspace sizes per (op, dtype, acc, layout, trans, m, n, device): the
+# library resolves every pack width and accumulation mode to answer, about as
+# long as the launch itself for a small reduction.  The cache is cleared
+# whenever the configuration table changes through this module; a table
+# changed behind it can only make a call report BWLA_ERR_WORKSPACE, on which
+# _with_workspace asks again once.
+_ws_sizes: dict = {}
+
+
 def workspace_size(op: int, dtype: torch.dtype, acc="plain", layout: int = L.ROW_MAJOR, trans: int = 0,
                    m: int = 0, n: int = 0) -> int:
-    out = ctypes.c_size_t(0)
-    check(lib.bwla_workspace_size(op, dtype_code(dtype), _ACC[acc], layout, trans, m, n, ctypes.byref(out)))
-    return out.value
+    key = (op, dtype, acc, layout, trans, m, n, torch.cuda.current_device() if torch.cuda.is_initialized() else -1)
+    v = _ws_sizes.get(key)
+    if v is None:
+        out = ctypes.c_size_t(0)
+        check(lib.bwla_workspace_size(op, dtype_code(dtype), _ACC[acc], layout, trans, m, n, ctypes.byref(out)))
+        v = out.value
+        if len(_ws_sizes) >= 4096:
+            _ws_sizes.clear()
+        _ws_sizes[key] = v
+    return v
+
+
+def _with_workspace(size_args, device, stream: ctypes.c_void_p, launch) -> None:
+    """Run launch(ws_pointer, ws_bytes) with the stream's workspace at the
+    cached size for ``size_args`` (the arguments of :func:`workspace_size`);
+    if the library reports the workspace too small, size it afresh and run
+    once more (nothing is enqueued by a call that fails validation)."""
+    st = launch(*_ws_ptr(workspace(workspace_size(*size_args), device, stream.value)))
+    if st == L.ERR_WORKSPACE:
+        _ws_sizes.clear()
+        st = launch(*_ws_ptr(workspace(workspace_size(*size_args), device, stream.value)))
+    check(st)
 
 
 # ---------------------------------------------------------------------------
@@ -189,9 +218,10 @@ def dot(x: torch.Tensor, y: torch.Tensor, acc="plain", out_dtype: torch.dtype | 
     if x.numel() != y.numel():
         raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
     out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
-    ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
-    check(lib.bwla_dot_strided(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, y.data_ptr(), incy,
-                               oc, out.data_ptr(), ws, wsn, _stream(x.device)))
+    args = (dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, y.data_ptr(), incy, oc, out.data_ptr())
+    stream = _stream(x.device)
+    _with_workspace((L.OP_DOT, x.dtype, acc, L.ROW_MAJOR, 0, 0, x.numel()), x.device, stream,
+                    lambda ws, wsn: lib.bwla_dot_strided(*args, ws, wsn, stream))
     return out
 
 
@@ -200,9 +230,10 @@ def nrm2(x: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
     """sqrt(<x, x>) as a 0-dim device tensor; strided 1-D views accepted."""
     incx = _svec(x, "x")
     out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
-    ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
-    check(lib.bwla_nrm2_strided(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, oc, out.data_ptr(),
-                                ws, wsn, _stream(x.device)))
+    args = (dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, oc, out.data_ptr())
+    stream = _stream(x.device)
+    _with_workspace((L.OP_DOT, x.dtype, acc, L.ROW_MAJOR, 0, 0, x.numel()), x.device, stream,
+                    lambda ws, wsn: lib.bwla_nrm2_strided(*args, ws, wsn, stream))
     return out
 
 
@@ -211,9 +242,10 @@ def asum(x: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
     """sum |x_i| as a 0-dim device tensor; strided 1-D views accepted."""
     incx = _svec(x, "x")
     out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
-    ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
-    check(lib.bwla_asum(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, oc, out.data_ptr(), ws, wsn,
-                        _stream(x.device)))
+    args = (dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), incx, oc, out.data_ptr())
+    stream = _stream(x.device)
+    _with_workspace((L.OP_DOT, x.dtype, acc, L.ROW_MAJOR, 0, 0, x.numel()), x.device, stream,
+                    lambda ws, wsn: lib.bwla_asum(*args, ws, wsn, stream))
     return out
 
 
@@ -256,10 +288,11 @@ def gemv(A: torch.Tensor, x: torch.Tensor, trans: bool = False, acc="plain",
     if y.numel() != out_len or y.dtype != od:
         raise BwlaError(L.ERR_INVALID_ARG, "out must have %d %s entries" % (out_len, od))
     if alpha == 1.0 and beta == 0.0 and incx == 1 and incy == 1:
-        op = L.OP_GEMV_ROWS
-        ws, wsn = _ws_ptr(workspace(workspace_size(op, A.dtype, acc, layout, int(trans), m, n), A.device))
-        check(lib.bwla_gemv(dtype_code(A.dtype), _ACC[acc], layout, int(trans), m, n, A.data_ptr(), lda,
-                            x.data_ptr(), _DTYPE[od], y.data_ptr(), ws, wsn, _stream(A.device)))
+        args = (dtype_code(A.dtype), _ACC[acc], layout, int(trans), m, n, A.data_ptr(), lda, x.data_ptr(),
+                _DTYPE[od], y.data_ptr())
+        stream = _stream(A.device)
+        _with_workspace((L.OP_GEMV_ROWS, A.dtype, acc, layout, int(trans), m, n), A.device, stream,
+                        lambda ws, wsn: lib.bwla_gemv(*args, ws, wsn, stream))
         return y
     nbytes = ctypes.c_size_t()
     check(lib.bwla_gemv_ex_workspace_size(dtype_code(A.dtype), _DTYPE[od], layout, int(trans), m, n,
@@ -331,10 +364,11 @@ def cg_update(alpha: float, x: torch.Tensor, p: torch.Tensor, r: torch.Tensor, q
     if alpha_dev is not None and (alpha_dev.dtype != compute_dtype(x.dtype) or alpha_dev.numel() != 1):
         raise BwlaError(L.ERR_INVALID_ARG, "alpha_dev must be one %s element" % compute_dtype(x.dtype))
     out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
-    ws, wsn = _ws_ptr(workspace(workspace_size(L.OP_DOT, x.dtype, acc, n=x.numel()), x.device))
-    check(lib.bwla_cg_update(dtype_code(x.dtype), _ACC[acc], x.numel(), float(alpha),
-                             None if alpha_dev is None else alpha_dev.data_ptr(), x.data_ptr(), p.data_ptr(),
-                             r.data_ptr(), q.data_ptr(), oc, out.data_ptr(), ws, wsn, _stream(x.device)))
+    args = (dtype_code(x.dtype), _ACC[acc], x.numel(), float(alpha), None if alpha_dev is None else alpha_dev.data_ptr(),
+            x.data_ptr(), p.data_ptr(), r.data_ptr(), q.data_ptr(), oc, out.data_ptr())
+    stream = _stream(x.device)
+    _with_workspace((L.OP_DOT, x.dtype, acc, L.ROW_MAJOR, 0, 0, x.numel()), x.device, stream,
+                    lambda ws, wsn: lib.bwla_cg_update(*args, ws, wsn, stream))
     return out
 
 
@@ -345,6 +379,7 @@ def set_config(op: int, dtype: torch.dtype, size_class: int = -1, acc=None, **fi
     """Set the configuration of (op, dtype, accumulation mode, size class); no
     fields = defaults.  acc None sets both accumulation modes."""
     a = -1 if acc is None else _ACC[acc]
+    _ws_sizes.clear()
     if fields:
         c = L.Config(**{k: int(v) for k, v in fields.items()})
         check(lib.bwla_set_config(op, dtype_code(dtype), a, size_class, ctypes.byref(c)))
@@ -359,6 +394,7 @@ def get_config(op: int, dtype: torch.dtype, m: int = 0, n: int = 0, acc="plain")
 
 
 def load_tuning(path: str) -> None:
+    _ws_sizes.clear()
     check(lib.bwla_load_tuning(path.encode()))
 
 

@@ -207,3 +207,41 @@ def test_multi_shape_pick_ranks_by_geometric_mean(monkeypatch):
     monkeypatch.setattr(tune, "time_ms", lambda fn, reps=10, warmup=2: slow[current["grid"]])
     cfg, score, rates = tune.multi_shape_pick(ws, cands, refine=3, refine_rounds=2)
     assert cfg["grid"] == 1024 and abs(score - 5000.0) < 1e-6 and len(rates) == 2
+
+
+def test_workspace_size_cache_and_retry(monkeypatch):
+    """ops caches workspace sizes, clears the cache when the configuration
+    table changes through ops, and runs a call once more with a fresh size
+    when the library reports the workspace too small (a table changed behind
+    the cache)."""
+    import torch
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    ops.reset_config()
+    try:
+        n = 1 << 22
+        a = ops.workspace_size(L.OP_DOT, torch.float32, "plain", n=n)
+        assert (L.OP_DOT, torch.float32, "plain", L.ROW_MAJOR, 0, 0, n, -1) in ops._ws_sizes
+        ops.set_config(L.OP_DOT, torch.float32, -1, grid=65536)
+        assert not ops._ws_sizes
+        b = ops.workspace_size(L.OP_DOT, torch.float32, "plain", n=n)
+        assert b >= 65536 * 16 > a
+        # a size cached before a change made with the raw C call is stale: the
+        # call is retried once with a fresh size
+        ops.reset_config()
+        ops.workspace_size(L.OP_DOT, torch.float32, "plain", n=n)
+        L.lib.bwla_set_config(L.OP_DOT, L.F32, -1, -1, ctypes_config(L, grid=65536))
+        sizes = []
+        monkeypatch.setattr(ops, "workspace", lambda nbytes, device, stream=None: sizes.append(nbytes) or None)
+        results = iter([L.ERR_WORKSPACE, L.OK])
+        import ctypes
+        ops._with_workspace((L.OP_DOT, torch.float32, "plain", L.ROW_MAJOR, 0, 0, n), None, ctypes.c_void_p(0),
+                            lambda ws, wsn: next(results))
+        assert sizes[0] < sizes[1] and sizes[1] >= 65536 * 16
+    finally:
+        ops.reset_config()
+
+
+def ctypes_config(L, **fields):
+    import ctypes
+    return ctypes.byref(L.Config(**fields))
