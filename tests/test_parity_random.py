@@ -1,0 +1,178 @@
+"""Seeded randomised parity sweep against the oracle.
+
+Each case draws its own shape, storage type, accumulation mode, layout,
+increments and library configuration from a fixed seed, so a failure names a
+reproducible case.  The configurations span the whole valid space, including
+ones the tuner never picks (one-lane groups, huge grids, ragged splits,
+work-group counts that turn into odd splits), on shapes with ragged tails and
+padded leading dimensions.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.batch_util import check as check_batch
+from tests.batch_util import from_sizes
+from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector
+from tests.gpu_util import DT, host, mat, need_gpu, vec
+
+pytestmark = pytest.mark.gpu
+
+CODE = {"f64": 0, "f32": 1, "bf16": 2}
+OUT = {"f64": 0, "f32": 1, "bf16": 1}
+DTYPES = ("f64", "f32", "bf16")
+ACCS = ("plain", "compensated")
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+    from paper_1409_0669_amd import ops
+    ops.reset_config()
+    yield
+    ops.reset_config()
+
+
+def _rng(kind, case):
+    return np.random.default_rng([2014, kind, case])
+
+
+def _logint(rng, lo, hi):
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+def _pick(rng, seq):
+    return seq[int(rng.integers(len(seq)))]
+
+
+def _rows_cfg(rng):
+    c = dict(block=64 * int(rng.integers(1, 17)), vec=_pick(rng, (1, 2, 4, 8, 16)), rows=_pick(rng, (1, 2, 4, 8)),
+             unroll=_pick(rng, (1, 2)))
+    if rng.random() < 0.5:
+        c["split"] = int(rng.integers(1, 10))
+    else:
+        c.update(split=0, grid=_pick(rng, (0, 1, 37, 256, 1000, 5000)))
+    return c
+
+
+def _cols_cfg(rng):
+    c = dict(block=64 * int(rng.integers(1, 17)), vec=_pick(rng, (1, 2, 4, 8, 16)),
+             unroll=_pick(rng, (1, 2, 4, 8)))
+    if rng.random() < 0.5:
+        c["split"] = int(rng.integers(1, 10))
+    else:
+        c.update(split=0, grid=_pick(rng, (0, 1, 37, 256, 1000, 5000)))
+    return c
+
+
+def _vec_cfg(rng, reduction):
+    return dict(block=64 * int(rng.integers(1, 17)), vec=_pick(rng, (1, 2, 4, 8, 16)),
+                unroll=_pick(rng, (1, 2, 4, 8) if reduction else (1, 2, 4)),
+                grid=_pick(rng, (0, 1, 3, 256, 2049, 20000)), increment=int(rng.integers(2)))
+
+
+@pytest.mark.parametrize("case", range(200))
+def test_random_gemv(case):
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    rng = _rng(1, case)
+    dtype, acc = _pick(rng, DTYPES), _pick(rng, ACCS)
+    layout, trans = _pick(rng, ("row", "col")), int(rng.integers(2))
+    m, n = _logint(rng, 1, 3000), _logint(rng, 1, 3000)
+    pad = _pick(rng, (0, 0, 1, 7, 64))
+    rows, cols = _rows_cfg(rng), _cols_cfg(rng)
+    what = "case %d: %s %s %s trans=%d %dx%d pad=%d rows=%s cols=%s" % (case, dtype, acc, layout, trans, m, n, pad,
+                                                                       rows, cols)
+    ops.set_config(L.OP_GEMV_ROWS, DT[dtype], -1, **rows)
+    ops.set_config(L.OP_GEMV_COLS, DT[dtype], -1, **cols)
+    A, A64 = mat(m, n, dtype, 70 + case % 5, layout=layout, pad=pad)
+    x, x64 = vec(m if trans else n, dtype, 75 + case % 5)
+    y = ops.gemv(A, x, trans=bool(trans), acc=acc)
+    B = A64.T if trans else A64
+    ref = oracle.gemv(np.ascontiguousarray(B), x64)
+    check_vector(host(y), ref, np.abs(B) @ np.abs(x64), TOL[dtype], what)
+
+
+@pytest.mark.parametrize("case", range(200))
+def test_random_reduction(case):
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    rng = _rng(2, case)
+    dtype, acc = _pick(rng, DTYPES), _pick(rng, ACCS)
+    op = _pick(rng, ("dot", "nrm2", "asum"))
+    n = 0 if rng.random() < 0.05 else _logint(rng, 1, 3_000_000)
+    incx, incy = _pick(rng, (1, 1, 1, 2, -1, -3)), _pick(rng, (1, 1, 2, -1, 0))
+    cfg = _vec_cfg(rng, True)
+    what = "case %d: %s %s %s n=%d incx=%d incy=%d cfg=%s" % (case, op, dtype, acc, n, incx, incy, cfg)
+    ops.set_config(L.OP_DOT, DT[dtype], -1, **cfg)
+    ops.set_config(L.OP_NRM2, DT[dtype], -1, **cfg)
+    x, x64 = vec(1 if n == 0 else (n - 1) * abs(incx) + 1, dtype, 80 + case % 5)
+    y, y64 = vec(1 if n == 0 else (n - 1) * abs(incy) + 1, dtype, 85 + case % 5)
+    od = torch.float64 if dtype == "f64" else torch.float32
+    out = torch.full((1,), -7.0, dtype=od, device="cuda")
+    wsn = ops.workspace_size(L.OP_DOT, DT[dtype], acc, n=n)
+    ws, wsb = ops._ws_ptr(ops.workspace(wsn, torch.device("cuda")))
+    a = L.ACC_COMPENSATED if acc == "compensated" else L.ACC_PLAIN
+    xs = oracle.strided(x64, n, incx)
+    if op == "dot":
+        L.check(L.lib.bwla_dot_strided(CODE[dtype], a, n, x.data_ptr(), incx, y.data_ptr(), incy, OUT[dtype],
+                                       out.data_ptr(), ws, wsb, ops._stream()))
+        ys = oracle.strided(y64, n, incy)
+        check_scalar(float(out.item()), oracle.dot(xs, ys), float(np.abs(xs * ys).sum()), TOL[dtype], what)
+    elif op == "nrm2":
+        L.check(L.lib.bwla_nrm2_strided(CODE[dtype], a, n, x.data_ptr(), incx, OUT[dtype], out.data_ptr(), ws, wsb,
+                                        ops._stream()))
+        check_scalar(float(out.item()), oracle.nrm2(xs), 0.0, TOL[dtype], what)
+    else:
+        L.check(L.lib.bwla_asum(CODE[dtype], a, n, x.data_ptr(), incx, OUT[dtype], out.data_ptr(), ws, wsb,
+                                ops._stream()))
+        check_scalar(float(out.item()), oracle.asum(xs), 0.0, TOL[dtype], what)
+
+
+@pytest.mark.parametrize("case", range(120))
+def test_random_axpby_bitwise(case):
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    rng = _rng(3, case)
+    dtype = _pick(rng, DTYPES)
+    n = _logint(rng, 1, 2_000_000)
+    incy, incz = _pick(rng, (1, 1, 2, -1, 0)), _pick(rng, (1, 1, -2, 3, 0))
+    incx = _pick(rng, (1, 1, 2, -3))
+    alpha, beta = float(rng.uniform(-2, 2)), _pick(rng, (0.0, 1.0, float(rng.uniform(-2, 2))))
+    cfg = _vec_cfg(rng, False)
+    what = "case %d: %s n=%d incs=%d,%d,%d a=%r b=%r cfg=%s" % (case, dtype, n, incy, incz, incx, alpha, beta, cfg)
+    ops.set_config(L.OP_AXPBY, DT[dtype], -1, **cfg)
+    y, y64 = vec((n - 1) * abs(incy) + 1, dtype, 90 + case % 5)
+    z, z64 = vec((n - 1) * abs(incz) + 1, dtype, 95 + case % 5)
+    x, x64 = vec((n - 1) * abs(incx) + 1, dtype, 100 + case % 5)
+    L.check(L.lib.bwla_axpby_strided(CODE[dtype], n, alpha, None, y.data_ptr(), incy, beta, None, z.data_ptr(), incz,
+                                     x.data_ptr(), incx, ops._stream()))
+    vals = oracle.axpby(dtype, oracle.scalar(dtype, alpha), oracle.strided(y64, n, incy), oracle.scalar(dtype, beta),
+                        oracle.strided(z64, n, incz))
+    assert bitwise_equal(host(x), oracle.scatter(x64, vals, incx)), what
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_random_batch(case):
+    from paper_1409_0669_amd.batch import BatchPlan
+    rng = _rng(4, case)
+    dtype, acc = _pick(rng, DTYPES), _pick(rng, ACCS)
+    ng, nd = int(rng.integers(1, 41)), int(rng.integers(0, 61))
+    Ms = np.array([_logint(rng, 1, 1500) for _ in range(ng)])
+    Ns = np.array([_logint(rng, 1, 20000 if rng.random() < 0.2 else 1500) for _ in range(ng)])
+    Ds = np.array([0 if rng.random() < 0.05 else _logint(rng, 1, 200_000) for _ in range(nd)])
+    align, block = _pick(rng, (1, 3, 8, 64)), _pick(rng, (64, 128, 256, 512))
+    what = "case %d: %s %s %d gemvs %d dots align=%d block=%d" % (case, dtype, acc, ng, nd, align, block)
+    gemvs, dots = from_sizes(dtype, Ms, Ns, Ds, seed=case, align=align)
+    plan = BatchPlan(gemvs, dots, acc=acc, block=block)
+    plan.run()
+    torch.cuda.synchronize()
+    try:
+        check_batch(dtype, gemvs, dots)
+    except AssertionError as e:
+        raise AssertionError("%s: %s" % (what, e)) from None
