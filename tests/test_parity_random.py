@@ -176,3 +176,130 @@ def test_random_batch(case):
         check_batch(dtype, gemvs, dots)
     except AssertionError as e:
         raise AssertionError("%s: %s" % (what, e)) from None
+
+
+def _strided_buf(n, inc, dtype, stream):
+    return vec(1 if n == 0 else (n - 1) * abs(inc) + 1, dtype, stream)
+
+
+@pytest.mark.parametrize("case", range(100))
+def test_random_gemv_ex(case):
+    """y <- alpha op(A) x + beta y with increments on x and y: the GEMV of
+    the oracle rounded to the output type, then its scaled addition; entries
+    of y between the strided elements stay untouched."""
+    import ctypes
+
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    rng = _rng(5, case)
+    dtype, acc = _pick(rng, DTYPES), _pick(rng, ACCS)
+    layout, trans = _pick(rng, ("row", "col")), int(rng.integers(2))
+    m, n = _logint(rng, 1, 2000), _logint(rng, 1, 2000)
+    pad = _pick(rng, (0, 1, 5))
+    incx, incy = _pick(rng, (1, 2, -1, -3)), _pick(rng, (1, 3, -1, -2))
+    alpha = _pick(rng, (1.0, -1.0, 0.0, float(rng.uniform(-3, 3))))
+    beta = _pick(rng, (0.0, 1.0, float(rng.uniform(-3, 3))))
+    rows, cols = _rows_cfg(rng), _cols_cfg(rng)
+    od = "f64" if dtype == "f64" else "f32"
+    what = "case %d: %s %s %s trans=%d %dx%d pad=%d incs=%d,%d a=%r b=%r rows=%s cols=%s" % (
+        case, dtype, acc, layout, trans, m, n, pad, incx, incy, alpha, beta, rows, cols)
+    ops.set_config(L.OP_GEMV_ROWS, DT[dtype], -1, **rows)
+    ops.set_config(L.OP_GEMV_COLS, DT[dtype], -1, **cols)
+    A, A64 = mat(m, n, dtype, 70 + case % 5, layout=layout, pad=pad)
+    out_len, in_len = (n, m) if trans else (m, n)
+    x, x64 = _strided_buf(in_len, incx, dtype, 75 + case % 5)
+    y, y64 = _strided_buf(out_len, incy, od, 80 + case % 5)
+    lda = A.stride(0) if layout == "row" else A.stride(1)
+    lay = L.ROW_MAJOR if layout == "row" else L.COL_MAJOR
+    nbytes = ctypes.c_size_t()
+    L.check(L.lib.bwla_gemv_ex_workspace_size(CODE[dtype], CODE[od], lay, trans, m, n, ctypes.byref(nbytes)))
+    ws, wsn = ops._ws_ptr(ops.workspace(nbytes.value, torch.device("cuda")))
+    L.check(L.lib.bwla_gemv_ex(CODE[dtype], L.ACC_COMPENSATED if acc == "compensated" else L.ACC_PLAIN, lay, trans,
+                               m, n, alpha, A.data_ptr(), lda, x.data_ptr(), incx, beta, CODE[od], y.data_ptr(), incy,
+                               ws, wsn, ops._stream()))
+    B = np.ascontiguousarray(A64.T if trans else A64)
+    xs, ys = oracle.strided(x64, in_len, incx), oracle.strided(y64, out_len, incy)
+    ref = oracle.gemv_axpby(od, alpha, B, xs, beta, ys)
+    scale = abs(alpha) * (np.abs(B) @ np.abs(xs)) + abs(beta) * np.abs(ys)
+    got = host(y)
+    check_vector(oracle.strided(got, out_len, incy), ref, scale, TOL[dtype], what)
+    mask = np.ones(got.size, bool)
+    mask[oracle._positions(out_len, incy)] = False
+    assert bitwise_equal(got[mask], y64[mask]), what
+
+
+@pytest.mark.parametrize("case", range(80))
+def test_random_gemv_dot(case):
+    """(y, <w, y>) in one launch sequence: y as the oracle's GEMV stored in
+    A's type, the inner product within 2 tol sum_i |w_i| (|op(A)| |x|)_i of
+    the oracle's <w, y>, and y bitwise what the GEMV alone stores."""
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    rng = _rng(6, case)
+    dtype, acc = _pick(rng, ("f64", "f32")), _pick(rng, ACCS)
+    layout, trans = _pick(rng, ("row", "col")), int(rng.integers(2))
+    m, n = _logint(rng, 1, 3000), _logint(rng, 1, 3000)
+    pad = _pick(rng, (0, 0, 3, 64))
+    rows, cols = _rows_cfg(rng), _cols_cfg(rng)
+    what = "case %d: %s %s %s trans=%d %dx%d pad=%d rows=%s cols=%s" % (case, dtype, acc, layout, trans, m, n, pad,
+                                                                       rows, cols)
+    ops.set_config(L.OP_GEMV_ROWS, DT[dtype], -1, **rows)
+    ops.set_config(L.OP_GEMV_COLS, DT[dtype], -1, **cols)
+    A, A64 = mat(m, n, dtype, 70 + case % 5, layout=layout, pad=pad)
+    x, x64 = vec(m if trans else n, dtype, 75 + case % 5)
+    w, w64 = vec(n if trans else m, dtype, 80 + case % 5)
+    y, s = ops.gemv_dot(A, x, w, trans=bool(trans), acc=acc)
+    B = np.ascontiguousarray(A64.T if trans else A64)
+    ref_y, ref_s = oracle.gemv_dot(dtype, B, x64, w64)
+    scale = np.abs(B) @ np.abs(x64)
+    check_vector(host(y), ref_y, scale, TOL[dtype], what + " y")
+    check_scalar(float(s.item()), ref_s, 2.0 * float(np.abs(w64) @ scale), TOL[dtype], what + " s")
+    assert bitwise_equal(host(y), host(ops.gemv(A, x, trans=bool(trans), acc=acc))), what
+
+
+@pytest.mark.parametrize("case", range(60))
+def test_random_ger_bitwise(case):
+    """A <- u v^T: every entry rounded once, padding between lines untouched."""
+    from paper_1409_0669_amd import ops
+    rng = _rng(7, case)
+    dtype, layout = _pick(rng, DTYPES), _pick(rng, ("row", "col"))
+    m, n = _logint(rng, 1, 3000), _logint(rng, 1, 3000)
+    pad = _pick(rng, (0, 1, 7, 64))
+    what = "case %d: %s %s %dx%d pad=%d" % (case, dtype, layout, m, n, pad)
+    A, _ = mat(m, n, dtype, 70 + case % 5, layout=layout, pad=pad)
+    u, u64 = vec(m, dtype, 75 + case % 5)
+    v, v64 = vec(n, dtype, 80 + case % 5)
+    base = A.t() if layout == "col" else A
+    before = host(base.as_strided((base.shape[0], base.stride(0)), (base.stride(0), 1)).contiguous())
+    ops.ger(u, v, A)
+    after = host(base.as_strided((base.shape[0], base.stride(0)), (base.stride(0), 1)).contiguous())
+    lda = base.stride(0)
+    ref = oracle.ger(dtype, u64, v64, layout=0 if layout == "row" else 1, lda=lda).reshape(-1, lda)
+    lines = base.shape[1]
+    assert bitwise_equal(after[:, :lines], ref[:, :lines]), what
+    assert bitwise_equal(after[:, lines:], before[:, lines:]), what
+
+
+@pytest.mark.parametrize("case", range(60))
+def test_random_cg_update(case):
+    """x <- x + a p, r <- r - a q bitwise the oracle's scaled additions, and
+    <r, r> of the new r within tolerance, under random configurations."""
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    rng = _rng(8, case)
+    dtype, acc = _pick(rng, DTYPES), _pick(rng, ACCS)
+    n = _logint(rng, 1, 2_000_000)
+    alpha = float(rng.uniform(-2, 2))
+    cfg = _vec_cfg(rng, True)
+    what = "case %d: %s %s n=%d a=%r cfg=%s" % (case, dtype, acc, n, alpha, cfg)
+    ops.set_config(L.OP_CG, DT[dtype], -1, **cfg)
+    x, x64 = vec(n, dtype, 70 + case % 5, dist="normal")
+    p, p64 = vec(n, dtype, 75 + case % 5, dist="normal")
+    r, r64 = vec(n, dtype, 80 + case % 5, dist="normal")
+    q, q64 = vec(n, dtype, 85 + case % 5, dist="normal")
+    rr = float(ops.cg_update(alpha, x, p, r, q, acc=acc).item())
+    ae = oracle.scalar(dtype, alpha)
+    rref = oracle.axpby(dtype, -ae, q64, 1.0, r64)
+    assert bitwise_equal(host(x), oracle.axpby(dtype, ae, p64, 1.0, x64)), what
+    assert bitwise_equal(host(r), rref), what
+    check_scalar(rr, oracle.dot(rref, rref), 0.0, TOL[dtype], what)
