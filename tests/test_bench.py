@@ -51,3 +51,20 @@ def test_bench_one_step_json():
     # working sets under the 256 MiB Infinity Cache are labelled, the 2^26 vectors and 16384^2 matrices are not
     assert "axpby f32 100000" in d["cache_resident"] and "gemv f64 rowx4096" in d["cache_resident"]
     assert "axpby f64 67108864" not in d["cache_resident"] and "gemv f64 rowx16384" not in d["cache_resident"]
+    # the f32 axpby at 2^26 stores a 256 MiB vector, which the cache can hold between back-to-back calls
+    assert d["write_cached"] == ["axpby f32 67108864"]
+
+
+def test_write_cached_rule():
+    """A row is flagged when its stores are at least 5 % of its bytes and fit
+    the 256 MiB Infinity Cache."""
+    sys.path.insert(0, ROOT)
+    import bench
+    mib = 1 << 20
+    assert bench._write_cached(768 * mib, 256 * mib)
+    assert not bench._write_cached(1536 * mib, 512 * mib)
+    assert not bench._write_cached(2048 * mib, 64 * 1024)  # a GEMV's output vector
+    assert not bench._write_cached(1024 * mib, 0)
+    assert bench._step_written(("axpby", "f32", 1 << 26)) == 256 * mib
+    assert bench._step_written(("dot", "f64", 1 << 26)) == 0
+    assert bench._step_written(("gemv", "f64", "row", 16384)) == 0
