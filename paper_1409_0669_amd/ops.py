@@ -37,8 +37,18 @@ def default_out_dtype(t: torch.dtype) -> torch.dtype:
     return torch.float64 if t == torch.float64 else torch.float32
 
 
-def _stream(device=None) -> ctypes.c_void_p:
-    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+# The raw handle of the current stream without building a torch Stream object
+# (which costs about 2 us per call, as much as a kernel launch).
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream(device=None) -> int:
+    """Handle of the current stream of ``device`` (a torch.device or None for
+    the current device), as the integer the C ABI takes for ``void *stream``."""
+    idx = device.index if device is not None and device.index is not None else None
+    if _raw_stream is not None:
+        return _raw_stream(torch.cuda.current_device() if idx is None else idx)
+    return torch.cuda.current_stream(device).cuda_stream
 
 
 def _vec(t: torch.Tensor, name: str) -> None:
@@ -83,7 +93,7 @@ def workspace(nbytes: int, device: torch.device, stream: int | None = None) -> t
     :func:`reserve_workspace`."""
     if nbytes == 0:
         return None
-    key = (device.index, torch.cuda.current_stream(device).cuda_stream if stream is None else stream)
+    key = (device.index, _stream(device) if stream is None else stream)
     with _ws_lock:
         buf = _ws.get(key)
         if buf is None or buf.numel() < nbytes:
@@ -99,7 +109,8 @@ def reserve_workspace(nbytes: int, device=None) -> None:
 
 
 def _ws_ptr(buf):
-    return (ctypes.c_void_p(buf.data_ptr()), buf.numel()) if buf is not None else (None, 0)
+    """(address, bytes) of a workspace buffer for the C ABI; (None, 0) for none."""
+    return (buf.data_ptr(), buf.numel()) if buf is not None else (None, 0)
 
 
 # Workspace sizes per (op, dtype, acc, layout, trans, m, n, device): the
@@ -113,7 +124,14 @@ _ws_sizes: dict = {}
 
 def workspace_size(op: int, dtype: torch.dtype, acc="plain", layout: int = L.ROW_MAJOR, trans: int = 0,
                    m: int = 0, n: int = 0) -> int:
-    key = (op, dtype, acc, layout, trans, m, n, torch.cuda.current_device() if torch.cuda.is_initialized() else -1)
+    return _ws_size(torch.cuda.current_device() if torch.cuda.is_initialized() else -1, op, dtype, acc, layout,
+                    trans, m, n)
+
+
+def _ws_size(dev: int, op: int, dtype: torch.dtype, acc, layout: int, trans: int, m: int, n: int) -> int:
+    """workspace_size on device index ``dev`` (the current device while the
+    library computes the size; -1 before torch has initialised HIP)."""
+    key = (op, dtype, acc, layout, trans, m, n, dev)
     v = _ws_sizes.get(key)
     if v is None:
         out = ctypes.c_size_t(0)
@@ -125,15 +143,21 @@ def workspace_size(op: int, dtype: torch.dtype, acc="plain", layout: int = L.ROW
     return v
 
 
-def _with_workspace(size_args, device, stream: ctypes.c_void_p, launch) -> None:
+def _with_workspace(size_args, device, stream: int, launch) -> None:
     """Run launch(ws_pointer, ws_bytes) with the stream's workspace at the
     cached size for ``size_args`` (the arguments of :func:`workspace_size`);
     if the library reports the workspace too small, size it afresh and run
-    once more (nothing is enqueued by a call that fails validation)."""
-    st = launch(*_ws_ptr(workspace(workspace_size(*size_args), device, stream.value)))
+    once more (nothing is enqueued by a call that fails validation).  The
+    tensors are on ``device``, which the caller's stream belongs to; the
+    sizes are cached under its index."""
+    if device is not None and device.index is not None:
+        dev = device.index
+    else:
+        dev = torch.cuda.current_device() if torch.cuda.is_initialized() else -1
+    st = launch(*_ws_ptr(workspace(_ws_size(dev, *size_args), device, stream)))
     if st == L.ERR_WORKSPACE:
         _ws_sizes.clear()
-        st = launch(*_ws_ptr(workspace(workspace_size(*size_args), device, stream.value)))
+        st = launch(*_ws_ptr(workspace(_ws_size(dev, *size_args), device, stream)))
     check(st)
 
 

@@ -19,10 +19,12 @@ best (the Table 2 analogue).
 
 The table has one entry per (operation, storage type, accumulation mode, size
 class).  The reducing operations are tuned once per accumulation mode
-(compensated arithmetic wants more waves in flight than plain); a GEMV size
-class is tuned on every workload shape that falls in it and keeps the
-candidate with the best geometric mean, its work-group count written so that
-the library derives each shape's split from it.
+(compensated arithmetic wants more waves in flight than plain).  Each size
+class is tuned on every workload that falls in it -- vector lengths that are
+powers of two and the paper-scale lengths 1e5, 1e6 and 1e7, GEMV shapes --
+and keeps the candidate with the best geometric mean over them; a GEMV entry
+is written as a work-group count, from which the library derives each shape's
+split.
 """
 from __future__ import annotations
 
@@ -246,6 +248,11 @@ def copy_proxy(results: dict) -> dict:
 
 
 # ---- the tuning run -------------------------------------------------------
+# Vector lengths tuned: powers of two spanning the size classes and the
+# lengths of the paper-scale workload (1e5, 1e6, 1e7); each class entry is
+# picked over every length that falls in the class.
+VEC_SIZES = (1 << 16, 10 ** 5, 10 ** 6, 1 << 20, 10 ** 7, 1 << 23, 1 << 25, 1 << 26)
+
 import os as _os
 
 DEFAULT_TABLE = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "tuning", "gfx950.txt")
@@ -293,14 +300,21 @@ GEMV_SHAPES = ((1024, 1024), (4096, 4096), (16384, 2048), (2048, 16384), (8192, 
 def multi_shape_pick(workloads, candidates, reps=6, refine=6, refine_rounds=5, log=None):
     """The candidate with the best geometric mean of GB/s over several
     workloads (shapes of one size class, all with the same table entry).
-    Every candidate is timed once per workload; the `refine` best by that
-    score are timed again round-robin over `refine_rounds` rounds and ranked
-    by the geometric mean of their medians.  Returns (best config, score in
-    GB/s, {workload index: GB/s of the best})."""
+    Every candidate is timed once per workload, then ranked as in
+    :func:`pick_from_sweeps`.  Returns (best config, score in GB/s,
+    {workload index: GB/s of the best})."""
+    sweeps = [sweep(w, candidates, reps=reps, log=log) for w in workloads]
+    return pick_from_sweeps(workloads, sweeps, reps=reps, refine=refine, refine_rounds=refine_rounds)
+
+
+def pick_from_sweeps(workloads, sweeps, reps=6, refine=6, refine_rounds=5):
+    """Rank the candidates that every sweep timed (sweeps[i] is a list of
+    (config, ms, GB/s) for workloads[i]) by the geometric mean of their GB/s
+    over the workloads; the `refine` best are timed again round-robin over
+    `refine_rounds` rounds and ranked by the geometric mean of their medians.
+    Returns (best config, score in GB/s, {workload index: GB/s of the best})."""
     keyf = lambda c: json.dumps(c, sort_keys=True)
-    per = []
-    for w in workloads:
-        per.append({keyf(c): (c, g) for c, _, g in sweep(w, candidates, reps=reps, log=log)})
+    per = [{keyf(c): (c, g) for c, _, g in res} for res in sweeps]
     common = [k for k in per[0] if all(k in p for p in per[1:])]
 
     def gmean(vals):
@@ -338,7 +352,6 @@ def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
     cus = L.lib.bwla_device_cus()
     ops.reset_config()
     entries, report = [], {"device": torch.cuda.get_device_name(), "cus": cus, "results": [], "copy_proxy": {}}
-    vec_sizes = (1 << 16, 1 << 20, 1 << 23, 1 << 25, 1 << 26)
     refine = 0 if quick else 6
 
     def record(w, res, default_ms, **where):
@@ -356,22 +369,35 @@ def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
         cands = _vector_candidates(dt, cus, quick)
         cands_red = _vector_candidates(dt, cus, quick, reduction=True)
         proxy_in = {}
-        for op in ("copy", "axpby", "dot", "nrm2", "cg"):
-            for acc in (("plain", "compensated") if op in REDUCING else ("plain",)):
-                best_for_class = {}
-                for n in vec_sizes:
-                    w = Workload(op, dt, n=n, acc=acc)
-                    default_ms = time_ms(w.run, reps=10)
-                    res = sweep(w, cands_red if op in ("dot", "nrm2") else cands, reps=6, refine=refine)
-                    best_for_class[w.cls] = res[0][0]  # larger sizes overwrite smaller ones in the same class
-                    record(w, res, default_ms, dn=dn, n=n)
-                    if n == vec_sizes[-1] and op != "cg" and acc == "plain":
-                        proxy_in[op] = res
-                    del w
-                for cls, cfg in best_for_class.items():
-                    entries.append((Workload_table_op(op), dt, acc if op in REDUCING else None, cls, cfg))
-        report["copy_proxy"][dn] = copy_proxy(proxy_in)
         es = torch.tensor([], dtype=dt).element_size()
+        for op in ("copy", "axpby", "dot", "nrm2", "cg"):
+            per_elem = {"copy": 2, "axpby": 3, "dot": 2, "nrm2": 1, "cg": 6}[op] * es
+            by_class = {}
+            for n in VEC_SIZES:
+                by_class.setdefault(size_class(per_elem * n), []).append(n)
+            for acc in (("plain", "compensated") if op in REDUCING else ("plain",)):
+                for cls, sizes in sorted(by_class.items()):
+                    # the workloads of one class live together: the pick re-times the leaders on each
+                    ws, sweeps, recs = [], [], []
+                    for n in sizes:
+                        w = Workload(op, dt, n=n, acc=acc)
+                        default_ms = time_ms(w.run, reps=10)
+                        res = sweep(w, cands_red if op in ("dot", "nrm2") else cands, reps=6, refine=refine)
+                        record(w, res, default_ms, dn=dn, n=n)
+                        recs.append(report["results"][-1])
+                        if n == VEC_SIZES[-1] and op != "cg" and acc == "plain":
+                            proxy_in[op] = res
+                        ws.append(w)
+                        sweeps.append(res)
+                    cfg, score, rates = pick_from_sweeps(ws, sweeps, refine=refine)
+                    for i, rec in enumerate(recs):
+                        rec["class_entry"], rec["class_entry_gbs"] = cfg, round(rates[i], 1)
+                    log("%-9s %-4s %-11s class %d entry over n=%s: %s, %s GB/s" % (
+                        op, dn, acc if op in REDUCING else "", cls, ",".join(str(n) for n in sizes), cfg,
+                        [round(rates[i], 1) for i in range(len(ws))]))
+                    entries.append((Workload_table_op(op), dt, acc if op in REDUCING else None, cls, cfg))
+                    del ws, sweeps
+        report["copy_proxy"][dn] = copy_proxy(proxy_in)
         by_class = {}
         for (m, n) in GEMV_SHAPES:
             by_class.setdefault(size_class((m * n + m + n) * es), []).append((m, n))

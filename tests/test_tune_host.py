@@ -234,8 +234,7 @@ def test_workspace_size_cache_and_retry(monkeypatch):
         sizes = []
         monkeypatch.setattr(ops, "workspace", lambda nbytes, device, stream=None: sizes.append(nbytes) or None)
         results = iter([L.ERR_WORKSPACE, L.OK])
-        import ctypes
-        ops._with_workspace((L.OP_DOT, torch.float32, "plain", L.ROW_MAJOR, 0, 0, n), None, ctypes.c_void_p(0),
+        ops._with_workspace((L.OP_DOT, torch.float32, "plain", L.ROW_MAJOR, 0, 0, n), None, 0,
                             lambda ws, wsn: next(results))
         assert sizes[0] < sizes[1] and sizes[1] >= 65536 * 16
     finally:
@@ -245,3 +244,35 @@ def test_workspace_size_cache_and_retry(monkeypatch):
 def ctypes_config(L, **fields):
     import ctypes
     return ctypes.byref(L.Config(**fields))
+
+
+def test_vector_sizes_cover_every_class_and_the_workload_lengths():
+    """The tuned vector lengths include the paper-scale lengths and give every
+    size class that a 2^16 .. 2^26 vector can fall in at least one length, for
+    every operation and storage type."""
+    import torch
+    from paper_1409_0669_amd import tune
+    for n in (10 ** 5, 10 ** 6, 10 ** 7, 1 << 26):
+        assert n in tune.VEC_SIZES
+    for es in (8, 4, 2):
+        for per in (1, 2, 3, 6):
+            tuned = {tune.size_class(per * es * n) for n in tune.VEC_SIZES}
+            wanted = {tune.size_class(per * es * n) for n in range(1 << 16, (1 << 26) + 1, 1 << 14)}
+            assert wanted <= tuned, (es, per, wanted - tuned)
+
+
+def test_pick_from_sweeps_uses_every_length_of_a_class():
+    """The entry of a class is the best geometric mean over its lengths, not
+    the winner of the largest length."""
+    import torch
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import tune
+
+    class FakeW:
+        table_op, dtype, cls, table_acc, bytes = L.OP_DOT, torch.float64, 1, "plain", 1e6
+
+    a, b = dict(block=128, grid=1024), dict(block=512, grid=2048)
+    small = [(a, 1.0, 900.0), (b, 1.0, 100.0)]
+    large = [(b, 1.0, 5000.0), (a, 1.0, 4000.0)]
+    cfg, score, rates = tune.pick_from_sweeps([FakeW(), FakeW()], [small, large], refine=0)
+    assert cfg == a and rates == {0: 900.0, 1: 4000.0}
