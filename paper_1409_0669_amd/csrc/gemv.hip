@@ -151,7 +151,7 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
 template <typename T, int V, int U, bool COMP>
 __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const T *A, int64_t ld,
                                                     const T *v, DD *partials, void *out, int out_f64,
-                                                    int split, const T *w, DD *dparts)
+                                                    int split, const T *w, DD *dparts, int xchg)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -215,24 +215,42 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
         }
     }
 
-    // combine the waves' partial sums in wave order through LDS
-    __syncthreads();
-    DD *red = reinterpret_cast<DD *>(smem);
+    // Combine the waves' partial sums in wave order through LDS.  With xchg
+    // the launch gave every wave but the first (nw - 1) * TK pairs of dynamic
+    // LDS: all waves write at once and wave 0 adds them in wave order after
+    // one barrier.  Otherwise the waves hand over one at a time through the
+    // staging buffer.  Both orders of addition are the same.
     DD d[V];
 #pragma unroll
     for (int e = 0; e < V; ++e)
         d[e] = acc[e].to_dd();
-    for (int w = 1; w < nw; ++w) {
-        if (wave == w)
+    if (xchg) {
+        extern __shared__ DD xs[];
+        if (wave > 0)
 #pragma unroll
             for (int e = 0; e < V; ++e)
-                red[lane * V + e] = d[e];
+                xs[(wave - 1) * TK + lane * V + e] = d[e];
         __syncthreads();
         if (wave == 0)
+            for (int wv = 1; wv < nw; ++wv)
 #pragma unroll
-            for (int e = 0; e < V; ++e)
-                d[e] = combine<COMP>(d[e], red[lane * V + e]);
+                for (int e = 0; e < V; ++e)
+                    d[e] = combine<COMP>(d[e], xs[(wv - 1) * TK + lane * V + e]);
+    } else {
         __syncthreads();
+        DD *red = reinterpret_cast<DD *>(smem);
+        for (int wv = 1; wv < nw; ++wv) {
+            if (wave == wv)
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    red[lane * V + e] = d[e];
+            __syncthreads();
+            if (wave == 0)
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    d[e] = combine<COMP>(d[e], red[lane * V + e]);
+            __syncthreads();
+        }
     }
     if (wave == 0) {
 #pragma unroll
@@ -375,10 +393,15 @@ hipError_t launch_gemv_cols(int64_t L, int64_t K, bool comp, const void *A, int6
         return with_unroll_cols(c.unroll, [&](auto U) {
             return with_bool(comp, [&](auto CP) {
                 const int64_t tiles = (K + 64 * V.value - 1) / (64 * V.value);
+                // the one-barrier wave combine when its exchange area is small
+                // enough not to limit how many work-groups share a CU
+                const size_t xbytes = (size_t)(c.block / 64 - 1) * 64 * V.value * sizeof(DD);
+                const int xchg = xbytes > 0 && xbytes <= kColsXchgBytes;
                 hipLaunchKernelGGL((k_gemv_cols<T, V.value, U.value, CP.value>),
-                                   dim3((unsigned)(tiles * c.split)), dim3(c.block), 0, s, L, K,
-                                   (const T *)A, ld, (const T *)v, partials, out, out_f64, c.split,
-                                   (const T *)w, dparts);
+                                   dim3((unsigned)(tiles * c.split)), dim3(c.block),
+                                   (unsigned)(xchg ? xbytes : 0), s, L, K, (const T *)A, ld,
+                                   (const T *)v, partials, out, out_f64, c.split, (const T *)w,
+                                   dparts, xchg);
                 return hipGetLastError();
             });
         });

@@ -16,6 +16,7 @@ struct Cfg {
 
 // The workspace of a reduction holds its float64 partials (DD pairs).
 constexpr int kColsStageLines = 2048; // x entries staged in LDS per pass (cols kernel)
+constexpr size_t kColsXchgBytes = 32768; // largest dynamic LDS of the cols kernel's wave combine
 
 // Map a runtime value onto a compile-time constant for template dispatch.
 template <typename F> hipError_t with_vec(int v, F &&f)
