@@ -28,8 +28,10 @@ the best of the one-row-per-work-group configurations is reported as well.
 
 Every configuration is timed as the tuner times it (``tune.time_ms``: the
 median over repetitions of a HIP-event interval around four calls launched
-back to back, divided by four), so a rate is the one the operation sustains in
-a sequence of operations rather than one call's on an idle GPU.
+back to back, divided by four, each interval starting behind a 2 GiB torch
+sum), so a rate is the GPU's time for the operation in a sequence of
+operations, not one call's on an idle GPU nor the host's rate of issuing
+calls.
 
 Run on the GPU: ``python -m paper_1409_0669_amd.study --json OUT.json --md OUT.md``.
 """
@@ -93,6 +95,14 @@ def analyse_gemv(space, rates, copy_cfg):
 
 
 def run(sizes=(2_000_000, 1 << 26), dtype=torch.float64, reps=5, log=print):
+    tune._blocker = tune._Blocker()
+    try:
+        return _run(sizes, dtype, reps, log)
+    finally:
+        tune._blocker = None
+
+
+def _run(sizes, dtype, reps, log):
     cus = L.lib.bwla_device_cus()
     space = tune.vector_space(cus)
     ops.reset_config()

@@ -97,6 +97,25 @@ def size_class(nbytes: float) -> int:
 PIPELINE = 4  # calls per timed interval
 
 
+class _Blocker:
+    """Keeps the stream busy while the calls under test are issued: a torch
+    sum over a 2 GiB float64 buffer (a few hundred microseconds, reads only,
+    and no kernel of this library, so no table entry changes its length).
+    An interval that starts behind it holds the GPU's time for the calls
+    alone.  Without it a small operation is timed at the host's rate of
+    issuing calls (about 10 us each from Python), which hides every
+    configuration whose kernels finish sooner."""
+
+    def __init__(self, nbytes: int = 1 << 31):
+        self.buf = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+
+    def __call__(self):
+        self.buf.sum()
+
+
+_blocker = None  # a _Blocker while tune_all runs
+
+
 def time_ms(fn, reps: int = 10, warmup: int = 2, batch: int = PIPELINE) -> float:
     """Median duration of one fn() call: `reps` intervals, each bracketed by
     HIP events recorded on the current stream (the stream the library
@@ -104,12 +123,15 @@ def time_ms(fn, reps: int = 10, warmup: int = 2, batch: int = PIPELINE) -> float
     `batch`.  Back-to-back calls overlap each launch with the work before it,
     as a sequence of operations does; a call timed alone also holds the
     dispatch latency of an idle GPU (about 10 us), the same for every
-    configuration."""
+    configuration.  While the tuner runs, each interval starts behind the
+    blocker (see _Blocker), so it measures the GPU's time, not the host's."""
     for _ in range(warmup):
         fn()
     times = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if _blocker is not None:
+            _blocker()
         e0.record()
         for _ in range(batch):
             fn()
@@ -349,9 +371,19 @@ def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
     """Sweep every operation, storage type, accumulation mode (for the
     reducing operations) and size class; return the table entries and a
     report (best and default rates, copy proxy)."""
+    global _blocker
+    _blocker = _Blocker()
+    try:
+        return _tune_all(dtypes, quick, log)
+    finally:
+        _blocker = None
+
+
+def _tune_all(dtypes, quick, log):
     cus = L.lib.bwla_device_cus()
     ops.reset_config()
-    entries, report = [], {"device": torch.cuda.get_device_name(), "cus": cus, "results": [], "copy_proxy": {}}
+    entries, report = [], {"device": torch.cuda.get_device_name(), "cus": cus, "results": [], "copy_proxy": {},
+                           "timing": "GPU time: each interval starts behind a 2 GiB torch sum"}
     refine = 0 if quick else 6
 
     def record(w, res, default_ms, **where):
