@@ -159,6 +159,28 @@ def test_gemv_rows_unroll_keeps_the_order(dtype, acc):
         assert bitwise_equal(got[0], got[1]), split
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+def test_gemv_cols_wave_combine_paths_agree(dtype, acc):
+    """The cols kernel adds its waves' partials in wave order whether they
+    meet in dynamic LDS after one barrier (512 threads, 2-wide packs: 14 KiB)
+    or pass one wave at a time (8-wide packs: 56 KiB, over the 32 KiB limit);
+    pack width and unroll do not change which wave takes which line.  All
+    results are bitwise the same, with and without a split."""
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    m, n = 3000, 2500  # lda = 3000 keeps 8-wide packs aligned
+    A, _ = mat(m, n, dtype, 41, layout="col")
+    x, _ = vec(n, dtype, 42)
+    for split in (1, 3):
+        got = []
+        for v, u in ((2, 4), (8, 4), (8, 1)):
+            ops.set_config(L.OP_GEMV_COLS, DT[dtype], -1, block=512, vec=v, unroll=u, split=split)
+            assert ops.get_config(L.OP_GEMV_COLS, DT[dtype], m, n, acc=acc)["vec"] == v
+            got.append(host(ops.gemv(A, x, acc=acc)))
+        assert bitwise_equal(got[0], got[1]) and bitwise_equal(got[0], got[2]), split
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_gemv_deterministic(dtype):
     from paper_1409_0669_amd import ops

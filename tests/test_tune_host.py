@@ -276,3 +276,34 @@ def test_pick_from_sweeps_uses_every_length_of_a_class():
     large = [(b, 1.0, 5000.0), (a, 1.0, 4000.0)]
     cfg, score, rates = tune.pick_from_sweeps([FakeW(), FakeW()], [small, large], refine=0)
     assert cfg == a and rates == {0: 900.0, 1: 4000.0}
+
+
+def test_time_ms_starts_each_interval_behind_the_blocker(monkeypatch):
+    """While a blocker is set, every timed interval is opened after it, so
+    the calls are issued while the stream is still busy; without one nothing
+    runs before the interval."""
+    from paper_1409_0669_amd import tune
+    trace = []
+
+    class FakeEvent:
+        def __init__(self, enable_timing=False):
+            self.t = None
+
+        def record(self):
+            trace.append("record")
+            self.t = len(trace)
+
+        def synchronize(self):
+            pass
+
+        def elapsed_time(self, other):
+            return float(other.t - self.t)
+
+    monkeypatch.setattr(tune.torch.cuda, "Event", FakeEvent)
+    monkeypatch.setattr(tune, "_blocker", lambda: trace.append("block"))
+    tune.time_ms(lambda: trace.append("call"), reps=2, warmup=1, batch=2)
+    assert trace == ["call"] + ["block", "record", "call", "call", "record"] * 2
+    trace.clear()
+    monkeypatch.setattr(tune, "_blocker", None)
+    tune.time_ms(lambda: trace.append("call"), reps=1, warmup=0, batch=1)
+    assert trace == ["record", "call", "record"]
