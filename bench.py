@@ -177,16 +177,21 @@ class TimingEvent:
             self._hip.hipEventDestroy(self.ev)
 
 
-def _median_ms(torch, fn, reps, batch=1):
+def _median_ms(torch, fn, reps, batch=1, blocker=None):
     """Median over `reps` of the HIP-event interval around `batch` calls of
     fn launched back to back, divided by `batch`.  batch = 1 times a call
     alone: the GPU idles between calls, so the interval holds the dispatch
     latency of every launch.  A batch of calls overlaps each launch with the
-    work before it, as in the timed step."""
+    work before it, as in the timed step.  With a blocker (a long kernel of
+    torch's own, enqueued before each interval) the calls are issued while
+    the stream is still busy, so the interval holds the GPU's time for them
+    rather than the host's time to issue them."""
     times = []
     fn()
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if blocker is not None:
+            blocker()
         e0.record()
         for _ in range(batch):
             fn()
@@ -559,9 +564,19 @@ def main():
     for name, nbytes, fn in work:
         ms = _median_ms(torch, fn, max(5, args.steps // 2), batch=PIPELINE)
         breakdown["%s %s %s" % (name[0], name[1], "x".join(map(str, name[2:])))] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    # The same rows in GPU time: each interval starts behind a 2 GiB torch
+    # sum, so calls that the host issues more slowly than the GPU runs them
+    # (the 1e5 and 1e6 rows) are timed by their kernels.
+    blk = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    breakdown_gpu = {}
+    for name, nbytes, fn in work:
+        ms = _median_ms(torch, fn, max(5, args.steps // 2), batch=PIPELINE, blocker=blk.sum)
+        breakdown_gpu["%s %s %s" % (name[0], name[1], "x".join(map(str, name[2:])))] = round(
+            nbytes / (ms * 1e-3) / 1e9, 1)
+    del blk
     if args.breakdown:
         for k, v in breakdown.items():
-            log("%-28s %9.1f GB/s" % (k, v))
+            log("%-28s %9.1f GB/s   GPU time %9.1f GB/s" % (k, v, breakdown_gpu[k]))
     # Rows whose working set fits the 256 MiB Infinity Cache: reported kernel
     # time only, no HBM-roofline claim.  Larger rows whose stored vector fits
     # it are listed apart: timed back to back, their stores can stay cached.
@@ -605,6 +620,7 @@ def main():
                                "4096^2, 16384^2 row- and column-major; f32 and f64; uniform[-1,1) seed 0",
                    "bytes_per_step": step_bytes, "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
         "roofline": roofline, "cpu_baseline": cpu, "copy_ceiling": copy_ceiling, "breakdown_gbs": breakdown,
+        "breakdown_gpu_gbs": breakdown_gpu,
         "cache_resident": cache_resident, "write_cached": write_cached, "other_rows": extra,
     }
     print(json.dumps(line), flush=True)

@@ -51,6 +51,8 @@ def test_bench_one_step_json():
     # working sets under the 256 MiB Infinity Cache are labelled, the 2^26 vectors and 16384^2 matrices are not
     assert "axpby f32 100000" in d["cache_resident"] and "gemv f64 rowx4096" in d["cache_resident"]
     assert "axpby f64 67108864" not in d["cache_resident"] and "gemv f64 rowx16384" not in d["cache_resident"]
+    # the same rows timed by the GPU (behind a blocker) as well as from the host
+    assert set(d["breakdown_gpu_gbs"]) == set(d["breakdown_gbs"]) and min(d["breakdown_gpu_gbs"].values()) > 0
     # the f32 axpby at 2^26 stores a 256 MiB vector, which the cache can hold between back-to-back calls
     assert d["write_cached"] == ["axpby f32 67108864"]
 
