@@ -175,7 +175,8 @@ def analyse(space, rates):
 
 def markdown(res) -> str:
     lines = ["# The paper's configuration study on %s (%d CUs)" % (res["device"], res["cus"]), "",
-             "%d configurations per operation, float64, fraction of the 8 TB/s HBM peak." % res["configs"], ""]
+             "%d configurations per operation, float64, fraction of the 8 TB/s HBM peak, in GPU time (four calls "
+             "per interval, each interval behind a 2 GiB torch sum)." % res["configs"], ""]
     for n, r in res["sizes"].items():
         t2 = r["table2"]
         lines += ["## n = %s" % n, "", "Single configuration chosen by the copy (Table 2 analogue): `%s`" % t2["config"], "",
