@@ -244,7 +244,7 @@ def extra_rows(torch, W, ops, reps):
     zb = torch.tensor([0.37], dtype=torch.float32, device="cuda")
     gx, gy = torch.empty_like(xv), torch.empty_like(yv)
     rate("adjoint dot backward f32 n=2^24", 4 * nd * 4,
-         lambda: (ops.axpby(1.0, yv, 0.0, yv, out=gx, alpha_dev=zb), ops.axpby(1.0, xv, 0.0, xv, out=gy, alpha_dev=zb)),
+         lambda: (ops.scal_to(1.0, yv, out=gx, alpha_dev=zb), ops.scal_to(1.0, xv, out=gy, alpha_dev=zb)),
          written=2 * nd * 4)
     del xv, yv, gx, gy
     # the copy, the paper's calibration kernel and tuning proxy (x <- y, 2ns bytes)

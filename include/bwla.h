@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BWLA_ABI_VERSION 2
+#define BWLA_ABI_VERSION 3
 
 typedef enum {
     BWLA_OK = 0,
@@ -171,6 +171,17 @@ bwla_status bwla_axpby_strided(bwla_dtype t, int64_t n, double alpha, const void
  * which forms 0 * z). */
 bwla_status bwla_scal(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev, void *x,
                       int64_t incx, void *stream);
+/* ---- out-of-place scaling: x <- alpha y, unit increments ------------------
+ * x_i = RN_t(a * y_i), a the effective factor as in bwla_axpby (alpha_dev,
+ * when given, is ONE device element of the compute type): one product and
+ * one rounding per element, one read of y and one write of x.  This is the
+ * gradient of the inner product z = <x, y>: dz/dx_i = y_i, so for an
+ * incoming gradient zbar (left on the device as alpha_dev) dx = zbar * y and
+ * dy = zbar * x, each one call.  x may equal y exactly (then this is
+ * bwla_scal in place); partial overlap is an error, and so is alpha_dev
+ * inside x.  Nothing is enqueued for n == 0. */
+bwla_status bwla_scal_to(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev, const void *y,
+                         void *x, void *stream);
 /* Reductions with increments; workspace as for bwla_dot (bwla_workspace_size
  * with BWLA_OP_DOT, BWLA_OP_NRM2 or BWLA_OP_CG serves every increment). */
 bwla_status bwla_dot_strided(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, int64_t incx,
@@ -283,9 +294,11 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
  * Descriptor pointers must stay valid while the plan is used.
  * cfg (may be NULL) sets only the work-group size: cfg->block, a multiple
  * of 64 up to 512 (default 256); other fields are ignored.
- * A persistent work-queue kernel (a machine-sized grid drawing items from an
- * atomic counter) is used instead when BWLA_ENABLE_UNVALIDATED_BATCH=1 is set
- * at plan creation; its current form has not been validated on hardware. */
+ * (The library also holds a persistent work-queue form of this launch, a
+ * machine-sized grid drawing items from an atomic counter.  It has not been
+ * validated on hardware and is switched off: with
+ * BWLA_ENABLE_UNVALIDATED_BATCH=1 in the environment, plan creation returns
+ * BWLA_ERR_UNSUPPORTED instead of building a plan for it.) */
 typedef struct bwla_batch_plan bwla_batch_plan;
 typedef struct {
     const void *A;

@@ -248,10 +248,13 @@ def ger(prec, u, v, layout: int = ROW_MAJOR, lda: int | None = None) -> np.ndarr
 
 
 def dot_backward(prec, zbar: float, x, y):
-    """Gradient of z = <x, y>: dx_i = RN(zbar*y_i), dy_i = RN(zbar*x_i)."""
-    # Written as a scaled addition with beta = 0 and z = the scaled operand,
-    # the same call sequence the library's adjoint uses.
-    return (axpby(prec, zbar, y, 0.0, y), axpby(prec, zbar, x, 0.0, x))
+    """Gradient of z = <x, y> = sum_i x_i y_i: dz/dx_i = y_i and dz/dy_i = x_i,
+    so with the upstream gradient zbar, dx_i = RN(zbar*y_i) and
+    dy_i = RN(zbar*x_i): one IEEE product per element, rounded once to the
+    storage precision (``scal``).  ``zbar`` is the effective factor in the
+    compute precision.  Infinite, NaN and signed-zero entries scale as IEEE
+    products do (zbar*inf = +-inf, -zbar * +0 = -0)."""
+    return (scal(prec, zbar, y), scal(prec, zbar, x))
 
 
 def gemv_backward(prec, A, x, ybar, layout: int = ROW_MAJOR):

@@ -20,7 +20,7 @@ ACC_PLAIN, ACC_COMPENSATED = 0, 1
 INC_GLOBAL, INC_LOCAL = 0, 1
 OP_COPY, OP_AXPBY, OP_DOT, OP_GEMV_ROWS, OP_GEMV_COLS, OP_GER, OP_NRM2, OP_CG = range(8)
 OP_COUNT = 8
-ABI_VERSION = 2  # BWLA_ABI_VERSION of include/bwla.h
+ABI_VERSION = 3  # BWLA_ABI_VERSION of include/bwla.h
 
 STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "INVALID_ARG", ERR_UNSUPPORTED: "UNSUPPORTED",
                 ERR_WORKSPACE: "WORKSPACE", ERR_HIP: "HIP", ERR_NOT_CAPTURABLE: "NOT_CAPTURABLE"}
@@ -58,6 +58,7 @@ SIGNATURES = {
     "bwla_copy_strided": (c_int, [c_int, i64, vp, i64, vp, i64, vp]),
     "bwla_axpby_strided": (c_int, [c_int, i64, dbl, vp, vp, i64, dbl, vp, vp, i64, vp, i64, vp]),
     "bwla_scal": (c_int, [c_int, i64, dbl, vp, vp, i64, vp]),
+    "bwla_scal_to": (c_int, [c_int, i64, dbl, vp, vp, vp, vp]),
     "bwla_dot_strided": (c_int, [c_int, c_int, i64, vp, i64, vp, i64, c_int, vp, vp, sz, vp]),
     "bwla_nrm2_strided": (c_int, [c_int, c_int, i64, vp, i64, c_int, vp, vp, sz, vp]),
     "bwla_asum": (c_int, [c_int, c_int, i64, vp, i64, c_int, vp, vp, sz, vp]),

@@ -4,7 +4,8 @@
   kernel on the same bytes of A) and dA = ybar x^T (the rank-1 overwrite
   kernel, a bandwidth-bound write of A's size), each only when needed.
 * ``DotFn``: z = <x, y>.  Backward: dx = RN(zbar * y) and dy = RN(zbar * x),
-  scaled additions whose factor zbar stays on the device.
+  each one out-of-place scaling (one product per element, one read and one
+  write) whose factor zbar stays on the device.
 
 Storage types float64 and float32 (GEMV); float64, float32 and bfloat16 (dot).
 Results and gradients of reductions are in the compute precision.
@@ -52,9 +53,9 @@ class DotFn(torch.autograd.Function):
         zb = zbar.reshape(1).contiguous()
         dx = dy = None
         if ctx.needs_input_grad[0]:
-            dx = ops.axpby(1.0, y, 0.0, y, alpha_dev=zb)
+            dx = ops.scal_to(1.0, y, alpha_dev=zb)
         if ctx.needs_input_grad[1]:
-            dy = ops.axpby(1.0, x, 0.0, x, alpha_dev=zb)
+            dy = ops.scal_to(1.0, x, alpha_dev=zb)
         return dx, dy, None
 
 

@@ -1,5 +1,8 @@
-"""``BatchPlan``: many uneven row-major GEMVs and dots in one persistent launch,
-optionally captured in a HIP graph and replayed."""
+"""``BatchPlan``: many uneven row-major GEMVs and dots in one batched launch --
+one work-group per work item (row tiles of the GEMVs, chunks of the dots,
+largest first), a GEMV kernel and a dot kernel, then a finalize kernel that
+combines each dot's chunk partials in chunk order -- optionally captured in
+a HIP graph and replayed."""
 from __future__ import annotations
 
 import ctypes

@@ -667,6 +667,32 @@ bwla_status bwla_scal(bwla_dtype t, int64_t n, double alpha, const void *alpha_d
     return hip_check(e, "scal launch");
 }
 
+bwla_status bwla_scal_to(bwla_dtype t, int64_t n, double alpha, const void *alpha_dev, const void *y, void *x,
+                         void *stream)
+{
+    if (!valid_dtype(t))
+        return fail(BWLA_ERR_UNSUPPORTED, "dtype %d", t);
+    if (n < 0)
+        return fail(BWLA_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    if (n == 0)
+        return BWLA_OK;
+    if (!x || !y)
+        return fail(BWLA_ERR_INVALID_ARG, "NULL vector with n > 0");
+    const size_t b = n * dsize(t);
+    Span sx = span(x, b), sy = span(y, b);
+    if (overlaps(sx, sy) && !same(sx, sy))
+        return fail(BWLA_ERR_INVALID_ARG, "x partially overlaps y (only exact aliasing is allowed)");
+    if (alpha_dev && overlaps(sx, span(alpha_dev, t == BWLA_F64 ? 8 : 4)))
+        return fail(BWLA_ERR_INVALID_ARG, "the device scalar lies inside x");
+    // one read stream and one write stream, as the copy: its table entry
+    Cfg c = resolve_vector(BWLA_OP_COPY, t, BWLA_ACC_PLAIN, n, {x, y}, 2);
+    hipError_t e = by_type(t, [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        return launch_scal<T>(n, alpha, alpha_dev, y, x, c, (hipStream_t)stream);
+    });
+    return hip_check(e, "scal_to launch");
+}
+
 // Which kernel serves (layout, trans), and the line view of A.
 struct GemvPlan {
     bool rows;       // rows kernel (reduction along lines) or cols kernel
@@ -1175,8 +1201,8 @@ void plan_free(bwla_batch_plan *p)
 // Plans use the grouped launch (one work-group per item).  The persistent
 // work-queue kernel hung on hardware twice (a compiler-divergent loop around
 // its work draw; see batched.hip) and its corrected form has not been run on
-// a GPU yet, so plans use it only when BWLA_ENABLE_UNVALIDATED_BATCH=1 is set
-// at plan creation.
+// a GPU, so it stays switched off: a plan asked for it with
+// BWLA_ENABLE_UNVALIDATED_BATCH=1 is refused with BWLA_ERR_UNSUPPORTED.
 bool persistent_requested()
 {
     const char *v = getenv("BWLA_ENABLE_UNVALIDATED_BATCH");
@@ -1238,6 +1264,9 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         return st;
     if (cfg && cfg->block > 512)
         return fail(BWLA_ERR_INVALID_ARG, "batch work-groups hold at most 512 threads (block %d)", cfg->block);
+    if (persistent_requested())
+        return fail(BWLA_ERR_UNSUPPORTED, "the persistent batched kernel is switched off (not validated on "
+                                          "hardware); unset BWLA_ENABLE_UNVALIDATED_BATCH to use the grouped launch");
     const size_t es = dsize(t), os = out_t == BWLA_F64 ? 8 : 4;
     bool aligned = true;
     const int nv = native_vec(t);
@@ -1275,7 +1304,7 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
     p->out_t = out_t;
     p->vec = aligned ? nv : 1;
     p->block = cfg && cfg->block ? cfg->block : 256;
-    p->persistent = persistent_requested();
+    p->persistent = false;
     (void)hipGetDevice(&p->device);
 
     // work items, with their cost in bytes for the largest-first order

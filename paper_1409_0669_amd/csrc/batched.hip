@@ -2,15 +2,14 @@
 //
 // Two designs share the work-item list.  The grouped launch (k_grouped_gemv
 // and k_grouped_dot, below the persistent kernel) runs one work-group per
-// item.  The
-// persistent kernel (k_batched) keeps a grid sized to the machine busy from
-// an atomic work queue; it is launched only on explicit opt-in (see the
-// plan code in api.cpp).
+// item; it is the one plans use.  The persistent kernel (k_batched) keeps a
+// grid sized to the machine busy from an atomic work queue; it has not been
+// validated on hardware and plan creation refuses it (see api.cpp).
 //
 // The host flattens every problem into work items -- row tiles of a GEMV
 // (full row length) and fixed-size chunks of a dot -- ordered by decreasing
-// cost, and launches a grid sized to the machine.  The kernel is
-// wave-persistent: each wave64 repeatedly takes the next item from an atomic
+// cost.  The persistent kernel would launch a grid sized to the machine and
+// be wave-persistent: each wave64 repeatedly takes the next item from an atomic
 // counter (lane 0 draws, readfirstlane broadcasts) until the list is
 // exhausted, and reduces its item within the wave, so the kernel has no LDS
 // traffic and no work-group barriers -- waves never wait for each other and
@@ -101,7 +100,10 @@ template <typename T, int V, bool COMP>
 __global__ __launch_bounds__(1024) void k_batched(BatchArgs a)
 {
     const int lane = threadIdx.x & 63;
-    for (;;) {
+    // Each trip takes a distinct item from the counter, so no wave can make
+    // more than n_items trips; the bound ends the loop even if a draw went
+    // wrong.
+    for (int64_t trip = 0; trip <= a.n_items; ++trip) {
         // Every lane takes part in the draw (lane 0 adds 1, the others 0) and
         // readfirstlane then returns lane 0's value.  No branch here depends on
         // the lane: with the draw under `if (lane == 0)` the compiler may split

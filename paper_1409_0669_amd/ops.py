@@ -221,6 +221,23 @@ def scal(alpha: float, x: torch.Tensor, alpha_dev: torch.Tensor | None = None) -
     return x
 
 
+def scal_to(alpha: float, y: torch.Tensor, out: torch.Tensor | None = None,
+            alpha_dev: torch.Tensor | None = None) -> torch.Tensor:
+    """x <- alpha y out of place (x_i = RN(a y_i), one product per element);
+    contiguous 1-D tensors.  ``alpha_dev``: an optional one-element device
+    tensor of the compute dtype that multiplies alpha (the upstream gradient
+    of an inner product, left on the device)."""
+    _vec(y, "y")
+    x = torch.empty_like(y) if out is None else out
+    _vec(x, "out")
+    _same(y.dtype, y.device, x)
+    if x.numel() != y.numel():
+        raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
+    check(lib.bwla_scal_to(dtype_code(y.dtype), y.numel(), float(alpha), _dev_scalar(y, alpha_dev, "alpha_dev"),
+                           y.data_ptr(), x.data_ptr(), _stream(y.device)))
+    return x
+
+
 def _scalar_out(dtype, out_dtype, device, out):
     od = default_out_dtype(dtype) if out_dtype is None else out_dtype
     if od not in (torch.float64, torch.float32):

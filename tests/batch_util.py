@@ -6,7 +6,7 @@ import torch
 
 import oracle
 import workloads as W
-from tests.criteria import TOL, check_scalar, check_vector
+from tests.criteria import TOL, check_scalar, check_vector, cond_scale, plain_reduced
 from tests.gpu_util import host
 
 
@@ -48,17 +48,22 @@ def from_sizes(dtype, Ms, Ns, Ds, seed=0, align=64):
     return gemvs, dots
 
 
-def check(dtype, gemvs, dots, gi=None, di=None):
+def check(dtype, acc, gemvs, dots, gi=None, di=None):
+    """Every problem (or those indexed by gi, di) against the oracle under
+    the criteria of tests/criteria.py for storage ``dtype`` and accumulation
+    ``acc``."""
     gi = range(len(gemvs)) if gi is None else gi
     di = range(len(dots)) if di is None else di
     for i in gi:
         A, x, y = gemvs[i]
         A64, x64 = host(A), host(x)
         ref = oracle.gemv(A64, x64)
-        check_vector(host(y), ref, np.abs(A64) @ np.abs(x64), TOL[dtype], "gemv %d" % i)
+        check_vector(host(y), ref, np.abs(A64) @ np.abs(x64), TOL[dtype], "gemv %d" % i,
+                     plain_f32=plain_reduced(dtype, acc))
     for i in di:
         p, q, out = dots[i]
         p64, q64 = host(p), host(q)
-        check_scalar(float(out.item()), oracle.dot(p64, q64), float(np.abs(p64 * q64).sum()), TOL[dtype], "dot %d" % i)
+        check_scalar(float(out.item()), oracle.dot(p64, q64), cond_scale(dtype, acc, np.abs(p64 * q64).sum()),
+                     TOL[dtype], "dot %d" % i)
 
 

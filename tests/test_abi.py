@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version_and_strings(L):
-    assert L.lib.bwla_abi_version() == L.ABI_VERSION == 2
+    assert L.lib.bwla_abi_version() == L.ABI_VERSION == 3
     for st, name in [(0, b"ok"), (1, b"invalid argument"), (3, b"workspace too small"), (4, b"HIP error")]:
         assert L.lib.bwla_status_string(st) == name
 
@@ -227,6 +227,20 @@ def test_batch_plan_validation(L):
     assert lib.bwla_batch_replay(None, None) == L.ERR_INVALID_ARG
 
 
+def test_persistent_batch_is_refused(L, monkeypatch):
+    """The persistent work-queue kernel is switched off: asking for it fails
+    plan creation before any allocation or launch (the getenv is read at
+    every creation)."""
+    lib = L.lib
+    h = ctypes.c_void_p()
+    g = (L.GemvDesc * 1)()
+    d = (L.DotDesc * 1)()
+    monkeypatch.setenv("BWLA_ENABLE_UNVALIDATED_BATCH", "1")
+    assert lib.bwla_batch_plan_create(0, 0, 0, g, 0, d, 0, None, ctypes.byref(h)) == L.ERR_UNSUPPORTED
+    assert "switched off" in lib.bwla_last_error().decode()
+    assert not h.value
+
+
 def test_host_sizing_never_crashes_on_degenerate_shapes(L):
     """Workspace sizing and configuration resolution are host arithmetic; sweep
     them over empty, tiny and huge shapes for every op, layout and dtype."""
@@ -325,6 +339,14 @@ def test_strided_validation(L):
     assert lib.bwla_scal(0, 10, 2.0, None, None, 1, None) == L.ERR_INVALID_ARG
     assert lib.bwla_scal(0, 10, 2.0, X + 8, X, 1, None) == L.ERR_INVALID_ARG          # device scalar inside x
     assert lib.bwla_scal(0, 0, 2.0, None, None, 0, None) == L.OK
+    # out-of-place scaling (unit increments): exact aliasing only
+    assert lib.bwla_scal_to(0, -1, 2.0, None, Y, X, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_scal_to(6, 10, 2.0, None, Y, X, None) == L.ERR_UNSUPPORTED
+    assert lib.bwla_scal_to(0, 10, 2.0, None, None, X, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_scal_to(0, 10, 2.0, None, Y, None, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_scal_to(0, 10, 2.0, None, X + 8, X, None) == L.ERR_INVALID_ARG    # partial overlap
+    assert lib.bwla_scal_to(1, 10, 2.0, X + 36, Y, X, None) == L.ERR_INVALID_ARG      # device scalar inside x
+    assert lib.bwla_scal_to(0, 0, 2.0, None, None, None, None) == L.OK
     ws = FAKE + (3 << 30)
     for fn, args in ((lib.bwla_dot_strided, (X, 2, Y, -3)), ):
         assert fn(0, 0, 10, *args, 0, X + 8, ws, 1 << 20, None) == L.ERR_INVALID_ARG  # out inside x's span

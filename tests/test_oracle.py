@@ -422,6 +422,59 @@ def test_dot_backward_is_scaling(prec):
             assert Fraction(g[i]) == r
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_dot_backward_ieee_specials(prec):
+    """dz/dx_i = y_i exactly, so the gradient entry is one IEEE product: an
+    infinite y_i gives an infinity with the sign of zbar * y_i, a NaN stays
+    NaN, a zero keeps the sign of the product (-zbar * +0 = -0), and
+    zbar = 0 times an infinity is NaN.  A form with an extra 0 * y_i term
+    (a scaled addition with beta = 0) fails the first and the signed zeros."""
+    y = np.array([np.inf, -np.inf, np.nan, 0.0, -0.0, 1.5, -0.25])
+    x = np.array([2.0, -0.0, 0.0, np.inf, np.nan, -4.0, 8.0])
+    for zbar, dx_ref, dy_ref in (
+            (-2.0, [-np.inf, np.inf, np.nan, -0.0, 0.0, -3.0, 0.5],
+             [-4.0, 0.0, -0.0, -np.inf, np.nan, 8.0, -16.0]),
+            (0.5, [np.inf, -np.inf, np.nan, 0.0, -0.0, 0.75, -0.125],
+             [1.0, -0.0, 0.0, np.inf, np.nan, -2.0, 4.0]),
+            (0.0, [np.nan, np.nan, np.nan, 0.0, -0.0, 0.0, -0.0],
+             [0.0, -0.0, 0.0, np.nan, np.nan, -0.0, 0.0]),
+            (-0.0, [np.nan, np.nan, np.nan, -0.0, 0.0, -0.0, 0.0],
+             [-0.0, 0.0, -0.0, np.nan, np.nan, 0.0, -0.0])):
+        dx, dy = oracle.dot_backward(prec, oracle.scalar(prec, zbar), x, y)
+        for got, ref in ((dx, dx_ref), (dy, dy_ref)):
+            for g, r in zip(got, ref):
+                if math.isnan(r):
+                    assert math.isnan(g), (prec, zbar, got, ref)
+                else:
+                    assert g == r and math.copysign(1.0, g) == math.copysign(1.0, r), (prec, zbar, got, ref)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_dot_backward_matches_derivative_of_exact_dot(prec):
+    """The exact inner product is linear in each x_i with slope y_i (and in
+    each y_i with slope x_i): setting the entry to 1 and then to 0 changes
+    the exact sum (Fraction arithmetic) by the slope, so the gradient entry
+    is zbar times that difference, rounded once."""
+    n = 24
+    x, y = _vals(prec, n, 93), _vals(prec, n, 94)
+    zbar = oracle.scalar(prec, 0.8125)
+    dx, dy = oracle.dot_backward(prec, zbar, x, y)
+    comp = "f64" if prec == "f64" else "f32"
+
+    def slope_of(a, b, i):
+        a1, a0 = a.copy(), a.copy()
+        a1[i], a0[i] = 1.0, 0.0
+        return exact_dot(a1, b) - exact_dot(a0, b)
+
+    for i in range(n):
+        slope_x, slope_y = slope_of(x, y, i), slope_of(y, x, i)
+        for g, slope in ((dx[i], slope_x), (dy[i], slope_y)):
+            r = rn(Fraction(zbar) * slope, comp)
+            if prec == "bf16":
+                r = rn(r, "bf16")
+            assert Fraction(float(g)) == r
+
+
 def test_gemv_adjoint_identity_and_finite_differences():
     # <w, A x> is bilinear, so the central difference with h = 1e-6 has no
     # truncation error; what remains is rounding of order u*|L|/h.

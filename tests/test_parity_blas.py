@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import oracle
-from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector
+from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector, cond_scale, plain_reduced
 from tests.gpu_util import DT, host, mat, need_gpu, vec
 
 pytestmark = pytest.mark.gpu
@@ -134,6 +134,36 @@ def test_scal_ieee_specials(dtype):
     assert np.signbit(got[3]) and not np.signbit(got[4])
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n", [1, 7, 4099, (1 << 20) + 3])
+def test_scal_to_bitwise(dtype, n):
+    """x <- a y out of place, a from the host and from a device scalar (the
+    inner product's gradient form), against the oracle's one rounding per
+    element; y untouched."""
+    from paper_1409_0669_amd import ops
+    y, y64 = vec(n, dtype, 83)
+    x = ops.scal_to(-2.5, y)
+    assert bitwise_equal(host(x), oracle.scal(dtype, oracle.scalar(dtype, -2.5), y64))
+    zb = torch.tensor([0.37], dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda")
+    ops.scal_to(1.0, y, out=x, alpha_dev=zb)
+    assert bitwise_equal(host(x), oracle.scal(dtype, oracle.scalar(dtype, 1.0, float(zb.item())), y64))
+    assert bitwise_equal(host(y), y64)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_scal_to_ieee_specials_and_signed_zeros(dtype):
+    """One IEEE product per element: zbar * inf is an infinity, NaN stays
+    NaN, -zbar * +0 = -0, and 0 * inf = NaN -- where a scaled addition with
+    beta = 0 (an extra 0 * y term) gives NaN and +0."""
+    from paper_1409_0669_amd import ops
+    vals = np.array([np.inf, -np.inf, np.nan, -0.0, 0.0, 3.0, -0.5])
+    y = torch.tensor(vals, dtype=DT[dtype], device="cuda")
+    for a in (-2.0, 0.5, 0.0, -0.0):
+        zb = torch.tensor([a], dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda")
+        x = ops.scal_to(1.0, y, alpha_dev=zb)
+        assert bitwise_equal(host(x), oracle.scal(dtype, oracle.scalar(dtype, 1.0, a), host(y))), a
+
+
 # ---------------------------------------------------------------------------
 # reductions
 # ---------------------------------------------------------------------------
@@ -152,15 +182,14 @@ def test_dot_strided(dtype, n, incs):
         out = torch.zeros((), dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda")
         _check(_lib().lib.bwla_dot_strided(CODE[dtype], acc, n, x.data_ptr(), incx, y.data_ptr(), incy, OUT[dtype],
                                            out.data_ptr(), ws, wsn, _stream()))
-        check_scalar(float(out.item()), ref, absum, TOL[dtype], "dot %s n=%d incs=%s acc=%d" % (dtype, n, incs, acc))
+        check_scalar(float(out.item()), ref, cond_scale(dtype, acc, absum), TOL[dtype],
+                     "dot %s n=%d incs=%s acc=%d" % (dtype, n, incs, acc))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("n", [1, 33, 10007, 1 << 20, (1 << 22) + 5])
 @pytest.mark.parametrize("inc", [1, 2, -1, -3])
 def test_nrm2_and_asum_strided(dtype, n, inc):
-    if n > (1 << 20) and inc != 1:
-        pytest.skip("large sizes run at unit increment only")
     x, x64 = _buf(n, inc, dtype, 71)
     xs = oracle.strided(x64, n, inc)
     ws, wsn = _red_ws(dtype, n)
@@ -254,7 +283,8 @@ def test_gemv_ex(dtype, layout, trans, case):
         # alpha carries that, beta y is exact input
         scale = abs(alpha) * (np.abs(B) @ np.abs(xs)) + abs(beta) * np.abs(ys)
         got = host(yy)
-        check_vector(oracle.strided(got, out_len, incy), ref, scale, TOL[dtype], "gemv_ex case %d acc %d" % (case, acc))
+        check_vector(oracle.strided(got, out_len, incy), ref, scale, TOL[dtype], "gemv_ex case %d acc %d" % (case, acc),
+                     plain_f32=plain_reduced(dtype, acc))
         # entries between the strided elements of y are untouched
         mask = np.ones(got.size, bool)
         mask[oracle._positions(out_len, incy)] = False
@@ -303,7 +333,8 @@ def test_ops_accept_strided_views(dtype):
     yb, yb64 = vec(2 * n, dtype, 81)
     x, x64 = xb[::3], xb64[::3]
     y, y64 = yb[::2], yb64[::2]
-    check_scalar(float(ops.dot(x, y).item()), oracle.dot(x64, y64), float(np.abs(x64 * y64).sum()), TOL[dtype])
+    check_scalar(float(ops.dot(x, y).item()), oracle.dot(x64, y64), cond_scale(dtype, "plain", np.abs(x64 * y64).sum()),
+                 TOL[dtype])
     check_scalar(float(ops.nrm2(x).item()), oracle.nrm2(x64), 0.0, TOL[dtype])
     check_scalar(float(ops.asum(y, acc="compensated").item()), oracle.asum(y64), 0.0, TOL[dtype])
     out = torch.zeros(2 * n, dtype=DT[dtype], device="cuda")
@@ -318,5 +349,6 @@ def test_ops_accept_strided_views(dtype):
         z = torch.zeros(14, dtype=DT[dtype], device="cuda")
         ops.gemv(A, x, trans=True, out=z[::2], alpha=1.0)
         gz = host(z)
-        check_vector(gz[::2], oracle.gemv(np.ascontiguousarray(A64.T), x64), np.abs(A64.T) @ np.abs(x64), TOL[dtype])
+        check_vector(gz[::2], oracle.gemv(np.ascontiguousarray(A64.T), x64), np.abs(A64.T) @ np.abs(x64), TOL[dtype],
+                     plain_f32=plain_reduced(dtype, "plain"))
         assert not gz[1::2].any()

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from tests.criteria import TOL, bitwise_equal, check_vector
+from tests.criteria import TOL, bitwise_equal, check_vector, plain_reduced
 from tests.gpu_util import DT, host, mat, need_gpu, vec
 
 pytestmark = pytest.mark.gpu
@@ -44,7 +44,8 @@ def test_gemv(dtype, layout, trans, shape):
     for acc in ("plain", "compensated"):
         y = ops.gemv(A, x, trans=bool(trans), acc=acc)
         ref, scale = _ref(A64, x64, trans)
-        check_vector(host(y), ref, scale, TOL[dtype], "%s %s t=%d %s" % (dtype, layout, trans, acc))
+        check_vector(host(y), ref, scale, TOL[dtype], "%s %s t=%d %s" % (dtype, layout, trans, acc),
+                     plain_f32=plain_reduced(dtype, acc))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -122,7 +123,8 @@ def test_gemv_configs(dtype, cfg):
                 for acc in ("plain", "compensated"):
                     y = ops.gemv(A, x, trans=bool(trans), acc=acc)
                     ref, scale = _ref(A64, x64, trans)
-                    check_vector(host(y), ref, scale, TOL[dtype], "%s %s %s" % (cfg, layout, trans))
+                    check_vector(host(y), ref, scale, TOL[dtype], "%s %s %s %s" % (cfg, layout, trans, acc),
+                                 plain_f32=plain_reduced(dtype, acc))
 
 
 @pytest.mark.parametrize("acc", ["plain", "compensated"])
@@ -139,7 +141,8 @@ def test_gemv_shipped_table_on_differentiation_shapes(acc, shape):
         x, x64 = vec(m if trans else n, "f32", 29)
         y = ops.gemv(A, x, trans=bool(trans), acc=acc)
         ref, scale = _ref(A64, x64, trans)
-        check_vector(host(y), ref, scale, TOL["f32"], "%s %s trans=%d" % (acc, shape, trans))
+        check_vector(host(y), ref, scale, TOL["f32"], "%s %s trans=%d" % (acc, shape, trans),
+                     plain_f32=plain_reduced("f32", acc))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector
+from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector, plain_reduced
 from tests.gpu_util import DT, host, mat, need_gpu, vec
 
 pytestmark = pytest.mark.gpu
@@ -31,7 +31,7 @@ def _gpu():
     ops.reset_config()
 
 
-def _check(dtype, A64, x64, w64, trans, y, s, what):
+def _check(dtype, acc, A64, x64, w64, trans, y, s, what):
     """y against the oracle's GEMV (componentwise, condition-scaled), and s
     against the oracle's <w, RN(op(A) x)> within
     2 tol sum_i |w_i| (|op(A)| |x|)_i: each stored y_i may differ from the
@@ -40,7 +40,7 @@ def _check(dtype, A64, x64, w64, trans, y, s, what):
     B = A64.T if trans else A64
     ref_y, ref_s = oracle.gemv_dot(dtype, np.ascontiguousarray(B), x64, w64)
     scale = np.abs(B) @ np.abs(x64)
-    check_vector(host(y), ref_y, scale, TOL[dtype], what + " y")
+    check_vector(host(y), ref_y, scale, TOL[dtype], what + " y", plain_f32=plain_reduced(dtype, acc))
     check_scalar(float(s.item()), ref_s, 2.0 * float(np.abs(w64) @ scale), TOL[dtype], what + " s")
 
 
@@ -57,7 +57,7 @@ def test_gemv_dot(dtype, layout, trans, shape):
     for acc in ("plain", "compensated"):
         y, s = ops.gemv_dot(A, x, w, trans=bool(trans), acc=acc)
         assert y.dtype == DT[dtype] and s.dtype == DT[dtype]
-        _check(dtype, A64, x64, w64, trans, y, s, "%s %s t=%d %s %s" % (dtype, layout, trans, shape, acc))
+        _check(dtype, acc, A64, x64, w64, trans, y, s, "%s %s t=%d %s %s" % (dtype, layout, trans, shape, acc))
         # y is exactly what the GEMV alone stores (same kernel, same order)
         assert bitwise_equal(host(y), host(ops.gemv(A, x, trans=bool(trans), acc=acc)))
 
@@ -80,7 +80,7 @@ def test_gemv_dot_configs(dtype, cfg):
                 w, w64 = vec(n if trans else m, dtype, 46)
                 for acc in ("plain", "compensated"):
                     y, s = ops.gemv_dot(A, x, w, trans=bool(trans), acc=acc)
-                    _check(dtype, A64, x64, w64, trans, y, s, "cfg %d %s t=%d %s" % (cfg, layout, trans, acc))
+                    _check(dtype, acc, A64, x64, w64, trans, y, s, "cfg %d %s t=%d %s" % (cfg, layout, trans, acc))
 
 
 @pytest.mark.parametrize("layout", ["row", "col"])
@@ -94,7 +94,7 @@ def test_gemv_dot_cg_pair_alias_and_f64_dot(layout):
     for acc in ("plain", "compensated"):
         q, s = ops.gemv_dot(A, p, acc=acc, dot_dtype=torch.float64)
         assert s.dtype == torch.float64
-        _check("f32", A64, p64, p64, 0, q, s, "cg pair %s %s" % (layout, acc))
+        _check("f32", acc, A64, p64, p64, 0, q, s, "cg pair %s %s" % (layout, acc))
 
 
 def test_gemv_dot_exact_integers():

@@ -18,7 +18,7 @@ import torch
 import oracle
 from tests.batch_util import check as check_batch
 from tests.batch_util import from_sizes
-from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector
+from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector, cond_scale, plain_reduced
 from tests.gpu_util import DT, host, mat, need_gpu, vec
 
 pytestmark = pytest.mark.gpu
@@ -95,7 +95,7 @@ def test_random_gemv(case):
     y = ops.gemv(A, x, trans=bool(trans), acc=acc)
     B = A64.T if trans else A64
     ref = oracle.gemv(np.ascontiguousarray(B), x64)
-    check_vector(host(y), ref, np.abs(B) @ np.abs(x64), TOL[dtype], what)
+    check_vector(host(y), ref, np.abs(B) @ np.abs(x64), TOL[dtype], what, plain_f32=plain_reduced(dtype, acc))
 
 
 @pytest.mark.parametrize("case", range(200))
@@ -123,7 +123,8 @@ def test_random_reduction(case):
         L.check(L.lib.bwla_dot_strided(CODE[dtype], a, n, x.data_ptr(), incx, y.data_ptr(), incy, OUT[dtype],
                                        out.data_ptr(), ws, wsb, ops._stream()))
         ys = oracle.strided(y64, n, incy)
-        check_scalar(float(out.item()), oracle.dot(xs, ys), float(np.abs(xs * ys).sum()), TOL[dtype], what)
+        check_scalar(float(out.item()), oracle.dot(xs, ys), cond_scale(dtype, acc, np.abs(xs * ys).sum()), TOL[dtype],
+                     what)
     elif op == "nrm2":
         L.check(L.lib.bwla_nrm2_strided(CODE[dtype], a, n, x.data_ptr(), incx, OUT[dtype], out.data_ptr(), ws, wsb,
                                         ops._stream()))
@@ -173,7 +174,7 @@ def test_random_batch(case):
     plan.run()
     torch.cuda.synchronize()
     try:
-        check_batch(dtype, gemvs, dots)
+        check_batch(dtype, acc, gemvs, dots)
     except AssertionError as e:
         raise AssertionError("%s: %s" % (what, e)) from None
 
@@ -222,7 +223,7 @@ def test_random_gemv_ex(case):
     ref = oracle.gemv_axpby(od, alpha, B, xs, beta, ys)
     scale = abs(alpha) * (np.abs(B) @ np.abs(xs)) + abs(beta) * np.abs(ys)
     got = host(y)
-    check_vector(oracle.strided(got, out_len, incy), ref, scale, TOL[dtype], what)
+    check_vector(oracle.strided(got, out_len, incy), ref, scale, TOL[dtype], what, plain_f32=plain_reduced(dtype, acc))
     mask = np.ones(got.size, bool)
     mask[oracle._positions(out_len, incy)] = False
     assert bitwise_equal(got[mask], y64[mask]), what
@@ -252,7 +253,7 @@ def test_random_gemv_dot(case):
     B = np.ascontiguousarray(A64.T if trans else A64)
     ref_y, ref_s = oracle.gemv_dot(dtype, B, x64, w64)
     scale = np.abs(B) @ np.abs(x64)
-    check_vector(host(y), ref_y, scale, TOL[dtype], what + " y")
+    check_vector(host(y), ref_y, scale, TOL[dtype], what + " y", plain_f32=plain_reduced(dtype, acc))
     check_scalar(float(s.item()), ref_s, 2.0 * float(np.abs(w64) @ scale), TOL[dtype], what + " s")
     assert bitwise_equal(host(y), host(ops.gemv(A, x, trans=bool(trans), acc=acc))), what
 
