@@ -141,6 +141,23 @@ bwla_status bwla_axpby(bwla_dtype t, int64_t n, double alpha, const void *alpha_
 bwla_status bwla_dot(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
                      bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- inner product without a workspace -----------------------------------
+ * For callers that cannot allocate or pass device memory for partials (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes exactly what bwla_dot computes -- same kernels, same
+ * configuration, bitwise the same result -- but keeps the first stage's
+ * float64 partials in a static device array of the library (1 MiB per GPU,
+ * 65536 pairs, held from the first call on that GPU until the process
+ * ends) instead of a caller workspace.  It calls no allocating routine.  A
+ * configuration needing more partials than the array holds is refused with
+ * BWLA_ERR_WORKSPACE (the default and tuned configurations never do: the
+ * grid of a reduction is capped at 65536 work-groups).  Every call on one
+ * GPU shares that GPU's array: calls that may overlap on one GPU (several
+ * streams, several host threads) race and must be serialised by the caller.
+ * Arguments, errors and the n == 0 case are as for bwla_dot. */
+bwla_status bwla_dot_noalloc(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
+                             bwla_dtype out_t, void *out, void *stream);
+
 /* ---- Euclidean norm: out <- sqrt(<x, x>) (no overflow scaling) -------------
  * Same reduction as bwla_dot on (x, x), reading x once. */
 bwla_status bwla_nrm2(bwla_dtype t, bwla_acc acc, int64_t n, const void *x,

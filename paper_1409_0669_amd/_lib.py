@@ -51,6 +51,7 @@ SIGNATURES = {
     "bwla_axpby": (c_int, [c_int, i64, dbl, vp, vp, dbl, vp, vp, vp, vp]),
     "bwla_dot": (c_int, [c_int, c_int, i64, vp, vp, c_int, vp, vp, sz, vp]),
     "bwla_nrm2": (c_int, [c_int, c_int, i64, vp, c_int, vp, vp, sz, vp]),
+    "bwla_dot_noalloc": (c_int, [c_int, c_int, i64, vp, vp, c_int, vp, vp]),
     "bwla_gemv": (c_int, [c_int, c_int, c_int, c_int, i64, i64, vp, i64, vp, c_int, vp, vp, sz, vp]),
     "bwla_gemv_dot": (c_int, [c_int, c_int, c_int, c_int, i64, i64, vp, i64, vp, vp, vp, c_int, vp, vp,
                               sz, vp]),

@@ -500,25 +500,44 @@ bwla_status bwla_axpby(bwla_dtype t, int64_t n, double alpha, const void *alpha_
     return hip_check(e, "axpby launch");
 }
 
-// dot (kRedDot), nrm2 (kRedSq) and asum (kRedAbs), any increments.
-static bwla_status reduce_common(bwla_dtype t, bwla_acc acc, int mode, int64_t n, const void *x, int64_t incx,
-                                 const void *y, int64_t incy, bwla_dtype out_t, void *out, void *ws,
-                                 size_t ws_bytes, void *stream)
+// Bytes of bwla_dot_noalloc's static scratch (defined with it below).
+constexpr size_t kScratchBytes = (size_t)65536 * sizeof(DD);
+
+// dot (kRedDot), nrm2 (kRedSq) and asum (kRedAbs), any increments: the
+// validation (everything but the workspace) and the resolved launch.
+struct RedPlan {
+    bool packed; // unit increments: the packed kernels
+    Cfg c;       // their configuration (packed only)
+    size_t need; // workspace bytes the launch uses
+};
+
+// Workspace: the caller's (ws, ws_bytes), or with `scratch` the static
+// array of bwla_dot_noalloc (kScratchBytes).
+static bwla_status reduce_check(bwla_dtype t, bwla_acc acc, int mode, int64_t n, const void *x, int64_t incx,
+                                const void *y, int64_t incy, bwla_dtype out_t, void *out, void *ws,
+                                size_t ws_bytes, bool scratch, RedPlan *plan)
 {
     const bool two = mode == kRedDot;
-    const bool packed = incx == 1 && (!two || incy == 1);
-    const size_t es = valid_dtype(t) ? dsize(t) : 1;
-    Cfg c{};
-    size_t need = 0;
-    if (packed) {
-        c = resolve_vector(two ? BWLA_OP_DOT : BWLA_OP_NRM2, t, acc, n, {x, y}, two ? 2 : 1);
-        need = n > 0 ? ws_dot(c) : 0;
-    } else {
-        need = n > 0 ? ws_strided(n) : 0;
-    }
-    bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
+    plan->packed = incx == 1 && (!two || incy == 1);
+    plan->c = Cfg{};
+    plan->need = 0;
+    // dtype, mode, n and the output
+    bwla_status st = check_reduction(t, acc, n, out_t, out, nullptr, 0, 0);
     if (st)
         return st;
+    const size_t es = dsize(t);
+    if (plan->packed) {
+        plan->c = resolve_vector(two ? BWLA_OP_DOT : BWLA_OP_NRM2, t, acc, n, {x, y}, two ? 2 : 1);
+        plan->need = n > 0 ? ws_dot(plan->c) : 0;
+    } else {
+        plan->need = n > 0 ? ws_strided(n) : 0;
+    }
+    if (scratch && plan->need > kScratchBytes)
+        return fail(BWLA_ERR_WORKSPACE, "this configuration needs %zu bytes of partials; the static scratch of "
+                                        "bwla_dot_noalloc holds %zu", plan->need, kScratchBytes);
+    if (!scratch && plan->need && (!ws || ws_bytes < plan->need))
+        return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given%s", plan->need, ws_bytes,
+                    ws ? "" : " (NULL)");
     if (!sfits(n, incx, es) || (two && !sfits(n, incy, es)))
         return fail(BWLA_ERR_INVALID_ARG, "increment too large for n = %lld", (long long)n);
     if (n > 0 && (!x || (two && !y)))
@@ -527,6 +546,14 @@ static bwla_status reduce_common(bwla_dtype t, bwla_acc acc, int mode, int64_t n
     Span so = span(out, os);
     if (n > 0 && (overlaps(so, sspan(x, n, incx, es)) || (two && overlaps(so, sspan(y, n, incy, es)))))
         return fail(BWLA_ERR_INVALID_ARG, "out overlaps an input");
+    return BWLA_OK;
+}
+
+static bwla_status reduce_launch(const RedPlan &plan, bwla_dtype t, bwla_acc acc, int mode, int64_t n, const void *x,
+                                 int64_t incx, const void *y, int64_t incy, bwla_dtype out_t, void *out, void *ws,
+                                 void *stream)
+{
+    const bool two = mode == kRedDot;
     hipStream_t s = (hipStream_t)stream;
     if (n == 0)
         return hip_check(launch_fill_zero(out, 1, out_t == BWLA_F64, s), "fill launch");
@@ -534,18 +561,75 @@ static bwla_status reduce_common(bwla_dtype t, bwla_acc acc, int mode, int64_t n
     const int of64 = out_t == BWLA_F64;
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
-        if (packed)
-            return launch_dot<T>(n, comp, mode, x, two ? y : x, of64, out, ws, c, s);
+        if (plan.packed)
+            return launch_dot<T>(n, comp, mode, x, two ? y : x, of64, out, ws, plan.c, s);
         return launch_strided_reduce<T>(mode, n, comp, x, incx, two ? y : x, two ? incy : incx, of64, out, ws,
                                         strided_grid(n, true), s);
     });
     return hip_check(e, mode == kRedDot ? "dot launch" : mode == kRedSq ? "nrm2 launch" : "asum launch");
 }
 
+static bwla_status reduce_common(bwla_dtype t, bwla_acc acc, int mode, int64_t n, const void *x, int64_t incx,
+                                 const void *y, int64_t incy, bwla_dtype out_t, void *out, void *ws,
+                                 size_t ws_bytes, void *stream)
+{
+    RedPlan plan;
+    bwla_status st = reduce_check(t, acc, mode, n, x, incx, y, incy, out_t, out, ws, ws_bytes, false, &plan);
+    if (st)
+        return st;
+    return reduce_launch(plan, t, acc, mode, n, x, incx, y, incy, out_t, out, ws, stream);
+}
+
 bwla_status bwla_dot(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
                      bwla_dtype out_t, void *out, void *ws, size_t ws_bytes, void *stream)
 {
     return reduce_common(t, acc, kRedDot, n, x, 1, y, 1, out_t, out, ws, ws_bytes, stream);
+}
+
+// --- the inner product for callers that cannot allocate ----------------------
+// Its first-stage partials go to a file-scope device array instead of a
+// caller workspace.  kScratchBytes (above) covers every configuration of the packed
+// inner product: the grid of a reduction is capped at 65536 work-groups, one
+// float64 pair each.  Host code never passes `scratch` itself (its name is a
+// host-side stand-in): each device's address of it is looked up once, with
+// that device current, and kept in g_scratch_ptr.
+static __device__ __align__(256) DD scratch[kScratchBytes / sizeof(DD)];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+
+static bwla_status scratch_ptr(void **ptr)
+{
+    int dev = 0;
+    bwla_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st)
+        return st;
+    if (dev < 0 || dev >= 64)
+        return fail(BWLA_ERR_UNSUPPORTED, "device %d: the static scratch table holds devices 0..63", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (st)
+            return st;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return BWLA_OK;
+}
+
+bwla_status bwla_dot_noalloc(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, const void *y,
+                             bwla_dtype out_t, void *out, void *stream)
+{
+    RedPlan plan;
+    bwla_status st = reduce_check(t, acc, kRedDot, n, x, 1, y, 1, out_t, out, nullptr, 0, true, &plan);
+    if (st)
+        return st;
+    void *ws = nullptr;
+    if (plan.need && (st = scratch_ptr(&ws)) != BWLA_OK)
+        return st;
+    // every partial slot the second stage reads is written by this call's
+    // first stage: nothing in the scratch has to start at zero
+    return reduce_launch(plan, t, acc, kRedDot, n, x, 1, y, 1, out_t, out, ws, stream);
 }
 
 bwla_status bwla_nrm2(bwla_dtype t, bwla_acc acc, int64_t n, const void *x, bwla_dtype out_t,

@@ -266,6 +266,23 @@ def dot(x: torch.Tensor, y: torch.Tensor, acc="plain", out_dtype: torch.dtype | 
     return out
 
 
+def dot_noalloc(x: torch.Tensor, y: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """<x, y> as :func:`dot` computes it (bitwise the same), with the
+    partials in the library's static device scratch instead of a workspace:
+    nothing is allocated when ``out`` is given.  Contiguous 1-D tensors.
+    Calls that may overlap on one GPU race on that scratch."""
+    _vec(x, "x")
+    _vec(y, "y")
+    _same(x.dtype, x.device, y)
+    if x.numel() != y.numel():
+        raise BwlaError(L.ERR_INVALID_ARG, "length mismatch")
+    out, oc = _scalar_out(x.dtype, out_dtype, x.device, out)
+    check(lib.bwla_dot_noalloc(dtype_code(x.dtype), _ACC[acc], x.numel(), x.data_ptr(), y.data_ptr(), oc,
+                               out.data_ptr(), _stream(x.device)))
+    return out
+
+
 def nrm2(x: torch.Tensor, acc="plain", out_dtype: torch.dtype | None = None,
          out: torch.Tensor | None = None) -> torch.Tensor:
     """sqrt(<x, x>) as a 0-dim device tensor; strided 1-D views accepted."""

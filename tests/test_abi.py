@@ -315,6 +315,21 @@ def test_gemv_dot_workspace_size(L):
     assert lib.bwla_gemv_dot_workspace_size(0, 0, 0, 1, 5, None) == L.ERR_INVALID_ARG
 
 
+def test_dot_noalloc_validation(L):
+    """The no-workspace inner product validates like bwla_dot before any HIP
+    call (these run without a GPU)."""
+    lib = L.lib
+    X, Y, O = FAKE, FAKE + (1 << 30), FAKE + (2 << 30)
+    assert lib.bwla_dot_noalloc(0, 0, -1, X, Y, 0, O, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_dot_noalloc(9, 0, 10, X, Y, 0, O, None) == L.ERR_UNSUPPORTED
+    assert lib.bwla_dot_noalloc(0, 4, 10, X, Y, 0, O, None) == L.ERR_UNSUPPORTED      # accumulation mode
+    assert lib.bwla_dot_noalloc(0, 0, 10, X, Y, 1, O, None) == L.ERR_UNSUPPORTED      # f32 out of f64 data
+    assert lib.bwla_dot_noalloc(1, 0, 10, X, Y, 2, O, None) == L.ERR_UNSUPPORTED      # bf16 output
+    assert lib.bwla_dot_noalloc(0, 0, 10, X, Y, 0, None, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_dot_noalloc(0, 0, 10, None, Y, 0, O, None) == L.ERR_INVALID_ARG
+    assert lib.bwla_dot_noalloc(0, 0, 10, X, Y, 0, X + 16, None) == L.ERR_INVALID_ARG  # out inside x
+
+
 def test_strided_validation(L):
     """Increments: zero output increments, overlaps and oversize strides are
     caught before anything is enqueued.  Every call here fails validation
