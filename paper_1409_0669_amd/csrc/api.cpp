@@ -1255,6 +1255,8 @@ struct bwla_batch_plan {
     int grid = 0, block = 256, vec = 1;
     int64_t n_items = 0, n_dots = 0;
     int64_t n_gemv_items = 0; // grouped launch: GEMV items come first
+    int64_t n_staged_items = 0; // of those, the staged tiles come first
+    size_t stage_bytes = 0;     // dynamic LDS of the staged-tile kernel
     double bytes = 0;
     BatchItem *d_items = nullptr;
     BatchGemv *d_gemv = nullptr;
@@ -1307,6 +1309,7 @@ hipError_t enqueue_batch(bwla_batch_plan *p, hipStream_t s)
     a.items = p->d_items;
     a.n_items = p->n_items;
     a.n_gemv_items = p->n_gemv_items;
+    a.n_staged_items = p->n_staged_items;
     a.gemv = p->d_gemv;
     a.dots = p->d_dots;
     a.partials = p->d_partials;
@@ -1317,7 +1320,7 @@ hipError_t enqueue_batch(bwla_batch_plan *p, hipStream_t s)
         using T = std::remove_pointer_t<decltype(tag)>;
         if (p->persistent)
             return launch_batched<T>(a, p->acc == BWLA_ACC_COMPENSATED, p->grid, p->block, s);
-        return launch_grouped<T>(a, p->acc == BWLA_ACC_COMPENSATED, p->block, s);
+        return launch_grouped<T>(a, p->acc == BWLA_ACC_COMPENSATED, p->block, p->stage_bytes, s);
     });
     if (e != hipSuccess)
         return e;
@@ -1437,10 +1440,19 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         b.lanes = lanes;
         if (q.m == 0)
             continue;
-        const int64_t rpi = std::max<int64_t>(1, std::min<int64_t>(q.m, kTileElems / std::max<int64_t>(1, q.n)));
+        int64_t rpi = std::max<int64_t>(1, std::min<int64_t>(q.m, kTileElems / std::max<int64_t>(1, q.n)));
+        if (b.mode == kModeStaged && !p->persistent) {
+            // whole row batches per tile: a staged work-group holds block / lanes
+            // rows at a time, so a tile of a multiple of that leaves no slot idle
+            const int64_t slots = std::max<int64_t>(1, p->block / lanes);
+            if (rpi > slots)
+                rpi = rpi / slots * slots;
+            p->stage_bytes = std::max(p->stage_bytes, tile_stage_bytes((int)es, q.n, lanes));
+        }
         for (int64_t r0 = 0; r0 < q.m; r0 += rpi) {
             Work w{};
             w.it.kind = 0;
+            w.it.pad = b.mode == kModeStaged ? 0 : 1; // sort key: staged tiles first
             w.it.prob = i;
             w.it.begin = r0;
             w.it.end = std::min(q.m, r0 + rpi);
@@ -1482,10 +1494,18 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
         std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) { return a.cost > b.cost; });
     else
         std::stable_sort(work.begin(), work.end(), [](const Work &a, const Work &b) {
-            return a.it.kind != b.it.kind ? a.it.kind < b.it.kind : a.cost > b.cost;
+            if (a.it.kind != b.it.kind)
+                return a.it.kind < b.it.kind;
+            if (a.it.pad != b.it.pad)
+                return a.it.pad < b.it.pad;
+            return a.cost > b.cost;
         });
-    for (const Work &w : work)
+    for (const Work &w : work) {
         p->n_gemv_items += w.it.kind == 0;
+        p->n_staged_items += w.it.kind == 0 && w.it.pad == 0;
+    }
+    for (Work &w : work)
+        w.it.pad = 0;
     std::vector<BatchItem> items(work.size());
     for (size_t i = 0; i < work.size(); ++i)
         items[i] = work[i].it;

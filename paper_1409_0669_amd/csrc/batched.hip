@@ -214,49 +214,32 @@ __device__ __forceinline__ void gemv_tile_block(const BatchGemv &g, int64_t rb, 
 // elements, and the x entry of every A entry comes from LDS.  x is held
 // interleaved by column residue, xs[(c % V) * P + c / V], so the lanes of a
 // group -- which take consecutive packs -- read consecutive LDS words for each
-// element position of a pack, whatever the row's head.
+// element position of a pack, whatever the row's head.  The residue stride P
+// is congruent to G modulo 64, so groups of one wave whose rows start at
+// different residues read disjoint banks.
 //
-// A row belongs to a group of G lanes, G sized on the host so that each lane
-// owns about kStagedPacks packs of it: one trip issues all of them (the
-// row's head and tail elements too) before any arithmetic, and two
+// A row belongs to a group of G lanes (a compile-time constant here, so every
+// LDS and global offset within a trip is an immediate), G sized on the host
+// so that each lane owns about kStagedPacks packs of it.  One trip issues the
+// U packs of A and their U*V x entries before any arithmetic; two
 // accumulators per lane split the dependency chain.  Loop control is
 // wave-uniform; rows past the tile re-read its last row and are not stored.
-template <typename T, int V, bool COMP>
-__device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb, int64_t re, int out_f64,
-                                                 compute_t<T> *xs)
+template <typename T, int V, bool COMP, int G>
+__device__ __forceinline__ void staged_rows(const BatchGemv &g, int64_t rb, int64_t re, int out_f64,
+                                            const compute_t<T> *xs, int P)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
-    // packs in flight: all of a lane's packs for 2-element packs, half of
-    // them for 4- and 8-element packs (whose x values per trip would not fit
-    // the registers)
-    constexpr int U = V >= 4 ? kStagedPacks / 2 : kStagedPacks;
-    constexpr int SU = 8; // x entries in flight per thread while staging
+    // packs in flight per trip: 8 for 2-element packs, 4 for 4- and
+    // 8-element packs (whose x values per trip would not fit the registers)
+    constexpr int U = V >= 4 ? 4 : 8;
+    constexpr int RPW = 64 / G;
     const int n = (int)g.n;
-    const int P = (n + V - 1) / V;
-    const T *x = (const T *)g.x;
-    for (int c0 = threadIdx.x; c0 < n; c0 += SU * blockDim.x) {
-        C v[SU];
-#pragma unroll
-        for (int k = 0; k < SU; ++k) {
-            const int c = c0 + k * (int)blockDim.x;
-            v[k] = c < n ? widen(x[c]) : C(0);
-        }
-#pragma unroll
-        for (int k = 0; k < SU; ++k) {
-            const int c = c0 + k * (int)blockDim.x;
-            if (c < n)
-                xs[(c % V) * P + c / V] = v[k];
-        }
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int G = g.lanes;
-    const int rpw = 64 / G;
-    const int sub = lane / G, gl = lane - sub * G;
+    const int sub = lane / G, gl = lane % G;
     const T *A = (const T *)g.A;
-    const int64_t slots = (int64_t)nw * rpw;
-    for (int64_t base = rb + (int64_t)wave * rpw; base < re; base += slots) {
+    const int64_t slots = (int64_t)nw * RPW;
+    for (int64_t base = rb + (int64_t)wave * RPW; base < re; base += slots) {
         const int64_t r = base + sub;
         const T *row = A + (r < re ? r : re - 1) * g.lda;
         const int mis = (int)(((uintptr_t)row & 15) / sizeof(T)); // elements past a 16-byte boundary
@@ -268,28 +251,52 @@ __device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb,
         // of each; rows with G < V lanes finish them after the packs
         const T hv = gl < h ? row[gl] : T(0);
         const T tv = t0 + gl < n ? row[t0 + gl] : T(0);
-        int xo[V]; // LDS position of element e of pack q: xs[xo[e] + q]
+        // x entry of element e of this lane's k-th pack (column
+        // h + (gl + k G) V + e): xs[xo[e] + k G].  Word offsets from the LDS
+        // array itself (not pointers advanced in the loop), so that the
+        // reads stay LDS reads with immediate offsets.
+        int xo[V];
 #pragma unroll
         for (int e = 0; e < V; ++e)
-            xo[e] = ((h + e) % V) * P + (h + e) / V;
+            xo[e] = ((h + e) % V) * P + (h + e) / V + gl;
+        const T *ap = row + h + (int64_t)gl * V;
         Acc<C, COMP> acc[2];
         int p = gl;
         for (; p + (U - 1) * G < np; p += U * G) {
             Pack<T, V> av[U];
+            C xv[U][V];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                av[u] = load_pack_nt<T, V>(row + h + (int64_t)(p + u * G) * V);
+                av[u] = load_pack_nt<T, V>(ap + u * G * V);
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int e = 0; e < V; ++e)
-                    acc[u & 1].template add_prod<EXACT>(widen(av[u].v[e]), xs[xo[e] + p + u * G]);
-        }
-        for (; p < np; p += G) {
-            const Pack<T, V> a = load_pack_nt<T, V>(row + h + (int64_t)p * V);
+                    xv[u][e] = xs[xo[e] + u * G];
+            end_of_loads();
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    acc[u & 1].template add_prod<EXACT>(widen(av[u].v[e]), xv[u][e]);
+            ap += U * G * V;
 #pragma unroll
             for (int e = 0; e < V; ++e)
-                acc[0].template add_prod<EXACT>(widen(a.v[e]), xs[xo[e] + p]);
+                xo[e] += U * G;
+        }
+        for (; p < np; p += G) {
+            const Pack<T, V> a = load_pack_nt<T, V>(ap);
+            C xv[V];
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                xv[e] = xs[xo[e]];
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                acc[0].template add_prod<EXACT>(widen(a.v[e]), xv[e]);
+            ap += G * V;
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                xo[e] += G;
         }
         if (gl < h)
             acc[1].template add_prod<EXACT>(widen(hv), xs[(gl % V) * P + gl / V]);
@@ -300,10 +307,59 @@ __device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb,
         for (int k = t0 + gl + G; k < n; k += G)
             acc[1].template add_prod<EXACT>(widen(row[k]), xs[(k % V) * P + k / V]);
         DD d = combine<COMP>(acc[0].to_dd(), acc[1].to_dd());
+#pragma unroll
         for (int m = G >> 1; m >= 1; m >>= 1)
             d = combine<COMP>(d, shfl_xor_dd(d, m));
         if (gl == 0 && r < re)
             store_out(g.y, r, out_f64, d.hi + d.lo);
+    }
+}
+
+// Stages x (widened to the compute type) in LDS, then runs the rows of the
+// tile with the row-group size the host chose.  Contains a barrier: every
+// thread of the work-group calls it.
+template <typename T, int V, bool COMP>
+__device__ __forceinline__ void gemv_tile_staged(const BatchGemv &g, int64_t rb, int64_t re, int out_f64,
+                                                 compute_t<T> *xs)
+{
+    using C = compute_t<T>;
+    // Each thread stages whole pack columns q (x entries qV .. qV + V - 1 to
+    // words e * P + q), SQ columns per round so that 8 entries are in flight:
+    // consecutive threads then write consecutive words of each residue row,
+    // free of bank conflicts whatever P is.
+    constexpr int SQ = V >= 8 ? 1 : 8 / V;
+    const int n = (int)g.n;
+    const int G = __builtin_amdgcn_readfirstlane(g.lanes);
+    const int P = staged_stride(n, V, G);
+    const int nq = (n + V - 1) / V;
+    const T *x = (const T *)g.x;
+    for (int q0 = threadIdx.x; q0 < nq; q0 += SQ * blockDim.x) {
+        C v[SQ][V];
+#pragma unroll
+        for (int k = 0; k < SQ; ++k)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int c = (q0 + k * (int)blockDim.x) * V + e;
+                v[k][e] = c < n ? widen(x[c]) : C(0);
+            }
+#pragma unroll
+        for (int k = 0; k < SQ; ++k) {
+            const int q = q0 + k * (int)blockDim.x;
+            if (q < nq)
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    xs[e * P + q] = v[k][e];
+        }
+    }
+    __syncthreads();
+    switch (G) {
+    case 1: staged_rows<T, V, COMP, 1>(g, rb, re, out_f64, xs, P); break;
+    case 2: staged_rows<T, V, COMP, 2>(g, rb, re, out_f64, xs, P); break;
+    case 4: staged_rows<T, V, COMP, 4>(g, rb, re, out_f64, xs, P); break;
+    case 8: staged_rows<T, V, COMP, 8>(g, rb, re, out_f64, xs, P); break;
+    case 16: staged_rows<T, V, COMP, 16>(g, rb, re, out_f64, xs, P); break;
+    case 32: staged_rows<T, V, COMP, 32>(g, rb, re, out_f64, xs, P); break;
+    default: staged_rows<T, V, COMP, 64>(g, rb, re, out_f64, xs, P); break;
     }
 }
 
@@ -356,22 +412,34 @@ __device__ __forceinline__ void dot_chunk_block(const BatchArgs &a, const BatchI
     }
 }
 
-// Two kernels: GEMV items (a.items[0, a.n_gemv_items)) and dot items (the
-// rest), so that each gets the registers of its own code paths.
+// Three kernels: staged GEMV items (a.items[0, a.n_staged_items)), the
+// other GEMV items (up to a.n_gemv_items) and dot items (the rest), so that
+// each gets the registers (and the staged tiles the LDS) of its own code
+// paths.  The staged kernel's x stage is dynamic LDS, sized by the plan for
+// its longest staged x.  Its waits on memory and LDS are hidden by other
+// waves, so it asks for 6 waves per SIMD where that costs no spills (f32:
+// 79 VGPRs); the bf16 and f64 forms are left to the compiler (98-130
+// VGPRs; asked for more waves, they spill).
 template <typename T, bool COMP>
-__global__ __launch_bounds__(512) void k_grouped_gemv(BatchArgs a)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value ? 6 : 1, 8)))
+void k_grouped_gemv_staged(BatchArgs a)
 {
     using C = compute_t<T>;
     constexpr int NATIVE = 16 / (int)sizeof(T);
-    __shared__ C xs[kTileStageBytes / sizeof(C)];
+    extern __shared__ __attribute__((aligned(16))) char stage[];
     const BatchItem w = a.items[blockIdx.x];
+    gemv_tile_staged<T, NATIVE, COMP>(a.gemv[w.prob], w.begin, w.end, a.out_f64, reinterpret_cast<C *>(stage));
+}
+
+template <typename T, bool COMP>
+__global__ __launch_bounds__(512) void k_grouped_gemv(BatchArgs a)
+{
+    constexpr int NATIVE = 16 / (int)sizeof(T);
+    const BatchItem w = a.items[a.n_staged_items + blockIdx.x];
     const BatchGemv &g = a.gemv[w.prob];
-    // the item is the same for every thread of the work-group; readfirstlane
-    // makes the branch visibly uniform (the staged tile holds a barrier)
+    // the item is the same for every thread of the work-group
     const int mode = __builtin_amdgcn_readfirstlane(g.mode);
-    if (mode == kModeStaged)
-        gemv_tile_staged<T, NATIVE, COMP>(g, w.begin, w.end, a.out_f64, xs);
-    else if (mode == kModePacked)
+    if (mode == kModePacked)
         gemv_tile_block<T, NATIVE, COMP>(g, w.begin, w.end, a.out_f64);
     else
         gemv_tile_block<T, 1, COMP>(g, w.begin, w.end, a.out_f64);
@@ -436,13 +504,19 @@ hipError_t launch_batched(const BatchArgs &a, bool comp, int grid, int block, hi
 template hipError_t launch_batched<BWLA_T>(const BatchArgs &, bool, int, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_grouped(const BatchArgs &a, bool comp, int block, hipStream_t s)
+hipError_t launch_grouped(const BatchArgs &a, bool comp, int block, size_t stage_bytes, hipStream_t s)
 {
     return with_bool(comp, [&](auto CP) {
-        const int64_t nd = a.n_items - a.n_gemv_items;
-        if (a.n_gemv_items > 0)
-            hipLaunchKernelGGL((k_grouped_gemv<T, CP.value>), dim3((unsigned)a.n_gemv_items), dim3(block), 0, s, a);
+        const int64_t ng = a.n_gemv_items - a.n_staged_items, nd = a.n_items - a.n_gemv_items;
+        if (a.n_staged_items > 0)
+            hipLaunchKernelGGL((k_grouped_gemv_staged<T, CP.value>), dim3((unsigned)a.n_staged_items), dim3(block),
+                               (unsigned)stage_bytes, s, a);
         hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        if (ng > 0)
+            hipLaunchKernelGGL((k_grouped_gemv<T, CP.value>), dim3((unsigned)ng), dim3(block), 0, s, a);
+        e = hipGetLastError();
         if (e != hipSuccess || nd <= 0)
             return e;
         hipLaunchKernelGGL((k_grouped_dot<T, CP.value>), dim3((unsigned)nd), dim3(block), 0, s, a);
@@ -450,7 +524,7 @@ hipError_t launch_grouped(const BatchArgs &a, bool comp, int block, hipStream_t 
     });
 }
 
-template hipError_t launch_grouped<BWLA_T>(const BatchArgs &, bool, int, hipStream_t);
+template hipError_t launch_grouped<BWLA_T>(const BatchArgs &, bool, int, size_t, hipStream_t);
 
 #if BWLA_T_IS_F64
 hipError_t launch_batch_reset(unsigned *counters, int64_t count, hipStream_t s)

@@ -156,11 +156,26 @@ enum {
     kModePacked = 1, // 16-byte packs of every operand (all of them 16-byte aligned)
     kModeScalar = 2  // one element per access
 };
-constexpr int kTileStageBytes = 32768; // LDS holding the staged x of a GEMV tile
-constexpr int kStagedPacks = 8;        // packs of a row each lane of a staged tile owns (and keeps in flight)
-// Longest x a staged tile takes, for storage elements of `es` bytes (x is
-// held in the compute precision: 8 bytes for f64, 4 otherwise).
-constexpr int tile_stage_elems(int es) { return kTileStageBytes / (es == 8 ? 8 : 4) - 16 / es; }
+constexpr int kTileStageBytes = 32768; // most LDS a staged GEMV tile's x may take
+constexpr int kStagedPacks = 16;       // packs of a row each lane of a staged tile owns (sets its row-group size)
+// Longest x a staged tile takes, for storage elements of `es` bytes: x is
+// held in the compute precision (8 bytes for f64, 4 otherwise) in V = 16/es
+// residue rows whose stride is at most ceil(n / V) + 64 words.
+constexpr int tile_stage_elems(int es) { return kTileStageBytes / (es == 8 ? 8 : 4) - 64 * (16 / es); }
+// Residue stride (words) of a staged x of n entries held in V residue rows
+// (column c at word (c % V) * stride + c / V), read by G-lane row groups: at
+// least ceil(n / V), and congruent to G modulo 64, so that row groups of one
+// wave whose rows start at different residues read disjoint LDS banks.
+__host__ __device__ constexpr int staged_stride(int64_t n, int V, int G)
+{
+    const int64_t p0 = (n + V - 1) / V;
+    return (int)(p0 + ((G - p0) % 64 + 64) % 64);
+}
+// LDS bytes of that staged x for storage elements of `es` bytes.
+constexpr size_t tile_stage_bytes(int es, int64_t n, int G)
+{
+    return (size_t)(16 / es) * (size_t)staged_stride(n, 16 / es, G) * (es == 8 ? 8 : 4);
+}
 struct BatchGemv {
     const void *A;
     int64_t m, n, lda;
@@ -181,6 +196,7 @@ struct BatchArgs {
     const BatchItem *items;
     int64_t n_items;
     int64_t n_gemv_items;   // grouped launch: items[0, n_gemv_items) are GEMV tiles, the rest dot chunks
+    int64_t n_staged_items; // grouped launch: of those, items[0, n_staged_items) are staged tiles
     const BatchGemv *gemv;
     const BatchDot *dots;
     double *partials;       // 2 doubles per dot chunk
@@ -191,9 +207,10 @@ struct BatchArgs {
 template <typename T>
 hipError_t launch_batched(const BatchArgs &a, bool comp, int grid, int block, hipStream_t s);
 hipError_t launch_batch_reset(unsigned *counters, int64_t count, hipStream_t s);
-// One work-group per item (a.n_items work-groups of `block` threads).
+// One work-group per item (a.n_items work-groups of `block` threads);
+// staged tiles get `stage_bytes` of dynamic LDS.
 template <typename T>
-hipError_t launch_grouped(const BatchArgs &a, bool comp, int block, hipStream_t s);
+hipError_t launch_grouped(const BatchArgs &a, bool comp, int block, size_t stage_bytes, hipStream_t s);
 // Combines the chunk partials of every multi-chunk dot, in chunk order.
 hipError_t launch_batch_finalize(const BatchDot *dots, int64_t nd, const double *partials, bool comp,
                                  int out_f64, hipStream_t s);

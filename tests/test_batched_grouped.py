@@ -146,7 +146,7 @@ def test_grouped_full_workload_every_problem(dtype):
 # x longer than the LDS stage of a GEMV tile: rows then use 16-byte packs when
 # A's rows and x are 16-byte aligned (n a multiple of the pack width) and
 # single elements otherwise; the shorter rows are staged at any alignment.
-STAGE = {"f64": 4094, "f32": 8188, "bf16": 8184}
+STAGE = {"f64": 3968, "f32": 7936, "bf16": 7680}  # tile_stage_elems: 32 KiB of x in V residue rows, stride padding up to 63 words
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
