@@ -307,8 +307,10 @@ def _rows_candidates(dtype, quick, cus=256):
 
 
 def _cols_candidates(dtype, quick, cus=256):
+    # one element per lane included: with few outputs the cols kernel's
+    # split (and its second kernel) grows with the pack width
     native = 16 // torch.tensor([], dtype=dtype).element_size()
-    vecs = (native,) if quick else (max(1, native // 2), native)
+    vecs = (native,) if quick else tuple(sorted({1, max(1, native // 2), native}))
     return [dict(block=b, vec=v, unroll=u, split=0, grid=g * cus) for b in (256, 512, 1024) for v in vecs
             for u in (2, 4, 8) for g in GEMV_GROUPS_PER_CU]
 
@@ -367,19 +369,29 @@ def _ger_candidates(dtype, quick):
             for v in (max(1, native // 2), native, min(16, 2 * native)) for r in (1, 2, 4, 8)]
 
 
-def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print):
-    """Sweep every operation, storage type, accumulation mode (for the
-    reducing operations) and size class; return the table entries and a
-    report (best and default rates, copy proxy)."""
+# what tune_all can tune; "gemv_row" / "gemv_col" are the rows and cols GEMV kernels
+ALL_OPS = ("copy", "axpby", "dot", "nrm2", "cg", "gemv_row", "gemv_col", "ger")
+
+
+def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print, ops_=ALL_OPS, vec_sizes=None,
+             gemv_shapes=None, ger_shapes=None, max_candidates=None, accs=("plain", "compensated")):
+    """Sweep every operation of `ops_`, storage type, accumulation mode (for
+    the reducing operations, of `accs`) and size class; return the table
+    entries and a report (best and default rates, copy proxy).  vec_sizes,
+    gemv_shapes and ger_shapes replace the workloads tuned on;
+    max_candidates keeps only the first candidates of each list (both for a
+    quick check of the tuner itself, not for a table)."""
     global _blocker
     _blocker = _Blocker()
     try:
-        return _tune_all(dtypes, quick, log)
+        return _tune_all(dtypes, quick, log, ops_, vec_sizes or VEC_SIZES, gemv_shapes or GEMV_SHAPES,
+                         ger_shapes or ((4096, 4096), (16384, 16384)), max_candidates, accs)
     finally:
         _blocker = None
 
 
-def _tune_all(dtypes, quick, log):
+def _tune_all(dtypes, quick, log, ops_, vec_sizes, gemv_shapes, ger_shapes, max_candidates, accs):
+    cut = (lambda c: c[:max_candidates]) if max_candidates else (lambda c: c)
     cus = L.lib.bwla_device_cus()
     ops.reset_config()
     entries, report = [], {"device": torch.cuda.get_device_name(), "cus": cus, "results": [], "copy_proxy": {},
@@ -398,16 +410,18 @@ def _tune_all(dtypes, quick, log):
 
     for dn in dtypes:
         dt = _DT[dn]
-        cands = _vector_candidates(dt, cus, quick)
-        cands_red = _vector_candidates(dt, cus, quick, reduction=True)
+        cands = cut(_vector_candidates(dt, cus, quick))
+        cands_red = cut(_vector_candidates(dt, cus, quick, reduction=True))
         proxy_in = {}
         es = torch.tensor([], dtype=dt).element_size()
         for op in ("copy", "axpby", "dot", "nrm2", "cg"):
+            if op not in ops_:
+                continue
             per_elem = {"copy": 2, "axpby": 3, "dot": 2, "nrm2": 1, "cg": 6}[op] * es
             by_class = {}
-            for n in VEC_SIZES:
+            for n in vec_sizes:
                 by_class.setdefault(size_class(per_elem * n), []).append(n)
-            for acc in (("plain", "compensated") if op in REDUCING else ("plain",)):
+            for acc in (accs if op in REDUCING else ("plain",)):
                 for cls, sizes in sorted(by_class.items()):
                     # the workloads of one class live together: the pick re-times the leaders on each
                     ws, sweeps, recs = [], [], []
@@ -417,7 +431,7 @@ def _tune_all(dtypes, quick, log):
                         res = sweep(w, cands_red if op in ("dot", "nrm2") else cands, reps=6, refine=refine)
                         record(w, res, default_ms, dn=dn, n=n)
                         recs.append(report["results"][-1])
-                        if n == VEC_SIZES[-1] and op != "cg" and acc == "plain":
+                        if n == vec_sizes[-1] and op != "cg" and acc == "plain":
                             proxy_in[op] = res
                         ws.append(w)
                         sweeps.append(res)
@@ -429,12 +443,16 @@ def _tune_all(dtypes, quick, log):
                         [round(rates[i], 1) for i in range(len(ws))]))
                     entries.append((Workload_table_op(op), dt, acc if op in REDUCING else None, cls, cfg))
                     del ws, sweeps
-        report["copy_proxy"][dn] = copy_proxy(proxy_in)
+        if "copy" in proxy_in:
+            report["copy_proxy"][dn] = copy_proxy(proxy_in)
         by_class = {}
-        for (m, n) in GEMV_SHAPES:
+        for (m, n) in gemv_shapes:
             by_class.setdefault(size_class((m * n + m + n) * es), []).append((m, n))
-        for layout, cands_g in (("row", _rows_candidates(dt, quick, cus)), ("col", _cols_candidates(dt, quick, cus))):
-            for acc in ("plain", "compensated"):
+        for layout, cands_g in (("row", cut(_rows_candidates(dt, quick, cus))),
+                                ("col", cut(_cols_candidates(dt, quick, cus)))):
+            if "gemv_" + layout not in ops_:
+                continue
+            for acc in accs:
                 for cls, shapes in sorted(by_class.items()):
                     ws = [Workload("gemv", dt, n=n, m=m, layout=layout, acc=acc) for (m, n) in shapes]
                     default = [w.bytes / (time_ms(w.run, reps=10) * 1e-3) / 1e9 for w in ws]
@@ -448,10 +466,10 @@ def _tune_all(dtypes, quick, log):
                         layout, dn, acc, cls, " ".join("%dx%d" % sh for sh in shapes), rec["best_gbs_per_shape"],
                         rec["default_gbs_per_shape"], cfg))
                     del ws
-        for (m, n) in ((4096, 4096), (16384, 16384)):
+        for (m, n) in (ger_shapes if "ger" in ops_ else ()):
             w = Workload("ger", dt, n=n, m=m)
             default_ms = time_ms(w.run, reps=10)
-            res = sweep(w, _ger_candidates(dt, quick), reps=6, refine=refine)
+            res = sweep(w, cut(_ger_candidates(dt, quick)), reps=6, refine=refine)
             entries.append((L.OP_GER, dt, None, w.cls, res[0][0]))
             record(w, res, default_ms, dn=dn, m=m, n=n)
             del w
@@ -462,17 +480,57 @@ def Workload_table_op(op: str) -> int:
     return {"copy": L.OP_COPY, "axpby": L.OP_AXPBY, "dot": L.OP_DOT, "nrm2": L.OP_NRM2, "cg": L.OP_CG}[op]
 
 
+def read_table(path: str):
+    """The entries of a tuning table as (op, dtype code, acc code, class,
+    config dict) tuples (the format write_table writes)."""
+    out = []
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if len(line) != 11:
+            continue
+        v = [int(t) for t in line]
+        out.append((v[0], v[1], v[2], v[3], dict(zip(("block", "vec", "unroll", "grid", "increment", "rows",
+                                                      "split"), v[4:]))))
+    return out
+
+
+def merge_entries(old, new_entries):
+    """old: read_table() rows; new_entries: tune_all() entries.  Returns
+    write_table() entries: the old ones, with every (op, dtype, acc, class)
+    that the new ones cover replaced, ordered by that key."""
+    code = {torch.float64: L.F64, torch.float32: L.F32, torch.bfloat16: L.BF16}
+    dt_of = {v: k for k, v in code.items()}
+    acc_of = {v: k for k, v in ACC_CODE.items()}
+    key = lambda op, dtc, accc, cls: (op, dtc, accc, cls)
+    covered = {key(op, code[dt], ACC_CODE[acc], cls) for op, dt, acc, cls, _ in new_entries}
+    kept = [(op, dt_of[dtc], acc_of[accc], cls, cfg) for op, dtc, accc, cls, cfg in old
+            if key(op, dtc, accc, cls) not in covered]
+    merged = kept + list(new_entries)
+    order = lambda e: (e[0], code[e[1]], ACC_CODE[e[2]], e[3])
+    return sorted(merged, key=order)
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="tune the bwla kernels on this GPU")
     ap.add_argument("--out", default=DEFAULT_TABLE, help="tuning table to write")
     ap.add_argument("--report", default=None, help="JSON report to write")
     ap.add_argument("--dtypes", default="f64,f32,bf16")
+    ap.add_argument("--ops", default=",".join(ALL_OPS), help="operations to tune: " + ",".join(ALL_OPS))
+    ap.add_argument("--merge", default=None,
+                    help="a table whose other entries are kept (the tuned ones are replaced)")
     ap.add_argument("--quick", action="store_true", help="smaller candidate lists")
     args = ap.parse_args(argv)
+    sel = tuple(args.ops.split(","))
+    bad = [o for o in sel if o not in ALL_OPS]
+    if bad:
+        ap.error("unknown operations %s" % bad)
     t0 = time.time()
+    old = read_table(args.merge) if args.merge else None  # before --out may overwrite it
     entries, report = tune_all(tuple(args.dtypes.split(",")), quick=args.quick,
-                               log=lambda *a: print(*a, flush=True))
+                               log=lambda *a: print(*a, flush=True), ops_=sel)
+    if old is not None:
+        entries = merge_entries(old, entries)
     _os.makedirs(_os.path.dirname(_os.path.abspath(args.out)), exist_ok=True)
     write_table(entries, args.out)
     if args.report:

@@ -1,0 +1,50 @@
+"""The autotuner itself on the GPU: a short run (two candidates per
+operation, small sizes) must time its candidates, write a table the library
+loads, and the operations must stay within the oracle's criteria when run
+with that table."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.criteria import TOL, check_scalar, check_vector, cond_scale
+from tests.gpu_util import host, mat, need_gpu, vec
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tuner_smoke_writes_a_table_the_library_uses(tmp_path):
+    need_gpu()
+    import torch
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops, tune
+    ops.reset_config()
+    try:
+        entries, report = tune.tune_all(("f32",), quick=True, log=lambda *a: None,
+                                        ops_=("dot", "gemv_row", "gemv_col"), vec_sizes=(1 << 16, 1 << 18),
+                                        gemv_shapes=((512, 384),), max_candidates=2, accs=("plain",))
+        kinds = {(op, cls) for op, _, _, cls, _ in entries}
+        assert (L.OP_DOT, 0) in kinds and (L.OP_DOT, 1) in kinds
+        assert {op for op, _, _, _, _ in entries} == {L.OP_DOT, L.OP_GEMV_ROWS, L.OP_GEMV_COLS}
+        assert all(r.get("best_gbs", r.get("best_gbs_geomean", 0)) > 0 for r in report["results"])
+        path = str(tmp_path / "table.txt")
+        tune.write_table(entries, path)
+        ops.load_tuning(path)
+        for op, _, acc, cls, cfg in entries:  # the library now resolves the tuned entries
+            if op == L.OP_DOT and cls == 1:  # 2^18 f32 elements of two vectors: 2 MiB
+                got = ops.get_config(L.OP_DOT, torch.float32, 0, 1 << 18)
+                assert (got["block"], got["unroll"]) == (cfg["block"], cfg["unroll"])
+        for n in (1 << 16, 100_003, 1 << 18):
+            x, x64 = vec(n, "f32", 1700)
+            y, y64 = vec(n, "f32", 1701)
+            check_scalar(float(ops.dot(x, y).item()), oracle.dot(x64, y64),
+                         cond_scale("f32", "plain", np.abs(x64 * y64).sum()), TOL["f32"], "dot %d" % n)
+        for layout in ("row", "col"):
+            A, A64 = mat(512, 384, "f32", 1702, layout=layout)
+            xv, xv64 = vec(384, "f32", 1703)
+            check_vector(host(ops.gemv(A, xv)), oracle.gemv(A64, xv64), np.abs(A64) @ np.abs(xv64), TOL["f32"],
+                         "gemv " + layout)
+    finally:
+        ops.reset_config()
+        ops.load_default_tuning()

@@ -89,6 +89,43 @@ def test_write_table_roundtrip(tmp_path):
             L.lib.bwla_set_config(op, L.F32, -1, -1, None)
 
 
+def test_read_and_merge_tables(tmp_path):
+    """A table read back equals what was written; merging replaces exactly
+    the (op, dtype, acc, class) entries the new ones cover."""
+    import torch
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import tune
+    p = str(tmp_path / "t.txt")
+    old = [(L.OP_AXPBY, torch.float32, None, 3, dict(block=512, vec=8, unroll=2, grid=2048, increment=1)),
+           (L.OP_GEMV_COLS, torch.float32, "plain", 2, dict(block=512, vec=2, unroll=8, grid=256)),
+           (L.OP_GEMV_COLS, torch.float32, "compensated", 2, dict(block=512, vec=2, unroll=8, grid=256)),
+           (L.OP_GEMV_COLS, torch.float64, "plain", 2, dict(block=256, vec=2, unroll=4, grid=512))]
+    tune.write_table(old, p)
+    back = tune.read_table(p)
+    assert [(o, d, a, c) for o, d, a, c, _ in back] == [(L.OP_AXPBY, L.F32, -1, 3), (L.OP_GEMV_COLS, L.F32, 0, 2),
+                                                         (L.OP_GEMV_COLS, L.F32, 1, 2), (L.OP_GEMV_COLS, L.F64, 0, 2)]
+    assert back[0][4] == dict(block=512, vec=8, unroll=2, grid=2048, increment=1, rows=0, split=0)
+    new = [(L.OP_GEMV_COLS, torch.float32, "plain", 2, dict(block=1024, vec=1, unroll=8, grid=256))]
+    merged = tune.merge_entries(back, new)
+    tune.write_table(merged, p)
+    rows = tune.read_table(p)
+    keys = [(o, d, a, c) for o, d, a, c, _ in rows]
+    assert keys == sorted(keys)                                     # written in key order
+    got = {k: cfg for k, (_, _, _, _, cfg) in zip(keys, rows)}
+    assert len(got) == 4
+    assert got[(L.OP_GEMV_COLS, L.F32, 0, 2)]["block"] == 1024 and got[(L.OP_GEMV_COLS, L.F32, 0, 2)]["vec"] == 1
+    assert got[(L.OP_GEMV_COLS, L.F32, 1, 2)]["block"] == 512       # the other mode is kept
+    assert got[(L.OP_GEMV_COLS, L.F64, 0, 2)]["unroll"] == 4        # the other type is kept
+    assert got[(L.OP_AXPBY, L.F32, -1, 3)]["increment"] == 1
+
+
+def test_cols_candidates_include_one_element_per_lane():
+    import torch
+    from paper_1409_0669_amd import tune
+    for dt, vecs in ((torch.float64, {1, 2}), (torch.float32, {1, 2, 4}), (torch.bfloat16, {1, 4, 8})):
+        assert {c["vec"] for c in tune._cols_candidates(dt, False)} == vecs
+
+
 def test_shipped_table_has_both_accumulation_modes():
     """The shipped table loads, and every reducing operation it tunes has an
     entry for each accumulation mode (elementwise operations: one shared)."""
