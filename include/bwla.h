@@ -45,7 +45,17 @@ extern "C" {
 
 #define BWLA_ABI_VERSION 3
 
-typedef enum {
+/* In C++ the enumerations below have int as their fixed underlying type, so
+ * every int a caller passes is a value of the parameter's type and the library
+ * can reject the ones it does not know (without it, an out-of-range value is
+ * undefined behaviour in C++).  In C an enumeration argument is an int. */
+#ifdef __cplusplus
+#define BWLA_ENUM_INT : int
+#else
+#define BWLA_ENUM_INT
+#endif
+
+typedef enum BWLA_ENUM_INT {
     BWLA_OK = 0,
     BWLA_ERR_INVALID_ARG = 1,   /* negative size, NULL pointer, bad lda, overlap */
     BWLA_ERR_UNSUPPORTED = 2,   /* dtype / accumulation / output-type combination */
@@ -54,8 +64,8 @@ typedef enum {
     BWLA_ERR_NOT_CAPTURABLE = 5 /* the call would allocate while the stream is capturing */
 } bwla_status;
 
-typedef enum { BWLA_F64 = 0, BWLA_F32 = 1, BWLA_BF16 = 2 } bwla_dtype;
-typedef enum { BWLA_ROW_MAJOR = 0, BWLA_COL_MAJOR = 1 } bwla_layout;
+typedef enum BWLA_ENUM_INT { BWLA_F64 = 0, BWLA_F32 = 1, BWLA_BF16 = 2 } bwla_dtype;
+typedef enum BWLA_ENUM_INT { BWLA_ROW_MAJOR = 0, BWLA_COL_MAJOR = 1 } bwla_layout;
 
 /* Accumulation of reductions.  PLAIN: one running sum per thread in the
  * compute precision.  COMPENSATED: the running sum carries its rounding error
@@ -64,14 +74,14 @@ typedef enum { BWLA_ROW_MAJOR = 0, BWLA_COL_MAJOR = 1 } bwla_layout;
  * f32 and only the sum is compensated (Kahan-style).  In both modes, partial
  * sums leave the thread as float64 and every combine across threads and
  * work-groups is done in float64 (double-float64 pairs when COMPENSATED). */
-typedef enum { BWLA_ACC_PLAIN = 0, BWLA_ACC_COMPENSATED = 1 } bwla_acc;
+typedef enum BWLA_ENUM_INT { BWLA_ACC_PLAIN = 0, BWLA_ACC_COMPENSATED = 1 } bwla_acc;
 
 /* Loop increment of the streaming kernels, the paper's two kernel skeletons
  * (Section 2): GLOBAL advances each thread by the whole grid; LOCAL gives each
  * work-group one contiguous chunk, advanced by the work-group size. */
-typedef enum { BWLA_INC_GLOBAL = 0, BWLA_INC_LOCAL = 1 } bwla_increment;
+typedef enum BWLA_ENUM_INT { BWLA_INC_GLOBAL = 0, BWLA_INC_LOCAL = 1 } bwla_increment;
 
-typedef enum {
+typedef enum BWLA_ENUM_INT {
     BWLA_OP_COPY = 0,
     BWLA_OP_AXPBY = 1,
     BWLA_OP_DOT = 2,

@@ -42,6 +42,9 @@ ROW_MAJOR, COL_MAJOR = 0, 1
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIBRARY may name another build of oracle.c (the sanitizer build of
+# build_sanitized()); by default the in-tree one is loaded.
+_LOAD = os.environ.get("ORACLE_LIBRARY") or _LIB
 
 _lib = None
 
@@ -57,13 +60,24 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(out_path: str) -> str:
+    """Compile ``oracle.c`` with gcc's AddressSanitizer and
+    UndefinedBehaviorSanitizer (any finding ends the process) into
+    ``out_path``; a process loads it with gcc's libasan preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-o", out_path, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    if _LOAD == _LIB and not os.path.exists(_LIB):
         build(force=False)
-    lib = ctypes.CDLL(_LIB)
+    lib = ctypes.CDLL(_LOAD)
     dp = ctypes.POINTER(ctypes.c_double)
     i64, c_int, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
     lib.o_round_bf16.argtypes = [dbl]

@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbwla.so")
+# BWLA_LIBRARY may name another build of the same sources (the host-sanitizer
+# build the CPU tests use); by default the in-tree library is loaded.
+LIB_PATH = os.environ.get("BWLA_LIBRARY") or os.path.join(HERE, "libbwla.so")
 
 # enums of bwla.h
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOT_CAPTURABLE = range(6)

@@ -69,5 +69,41 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB
 
 
+# Host AddressSanitizer + UndefinedBehaviorSanitizer on the API layer (argument
+# validation, workspace sizing, configuration tables, plan building): each
+# sanitizer flag goes to the host pass only, the kernels are the ordinary
+# objects.  The library leaves the sanitizer runtime's symbols undefined; a
+# process loads it with that runtime preloaded (SANITIZER_RUNTIME).
+ROCM_ROOT = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+SANITIZER_RUNTIME = os.path.join(ROCM_ROOT, "llvm", "lib", "clang")
+
+
+def sanitizer_runtime() -> str:
+    """Path of the clang AddressSanitizer runtime that hipcc's host pass
+    targets (it carries the UndefinedBehaviorSanitizer handlers too)."""
+    for ver in sorted(os.listdir(SANITIZER_RUNTIME), reverse=True):
+        p = os.path.join(SANITIZER_RUNTIME, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(p):
+            return p
+    raise FileNotFoundError("no libclang_rt.asan-x86_64.so under " + SANITIZER_RUNTIME)
+
+
+def build_sanitized(out_path: str) -> str:
+    """Builds a copy of the library whose API layer carries host ASan/UBSan
+    checks at ``out_path``; the kernel objects are those of build()."""
+    objs = [os.path.join(OBJDIR, f"{src[:-4]}_{t}.o") for src in KERNEL_SOURCES for t in TYPES]
+    if not all(os.path.exists(o) for o in objs):
+        build()
+    api_obj = out_path + ".api.o"
+    _run([HIPCC, *COMMON_FLAGS, "-O1", "-g",
+          "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+          "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+          "-x", "hip", "-c", os.path.join(CSRC, "api.cpp"), "-o", api_obj])
+    rocm_lib = os.path.join(ROCM_ROOT, "lib")
+    _run([os.path.join(ROCM_ROOT, "llvm", "bin", "clang++"), "-shared", "-fPIC", "-o", out_path, api_obj, *objs,
+          "-L" + rocm_lib, "-lamdhip64", "-Wl,-rpath," + rocm_lib])
+    return out_path
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

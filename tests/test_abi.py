@@ -46,6 +46,58 @@ def st(L, r):
     return r, L.lib.bwla_last_error().decode()
 
 
+def test_unknown_enum_values_are_rejected(L):
+    """Every entry point rejects a storage type, accumulation mode or output
+    type it does not know with the documented status, before any table
+    lookup (the host-sanitizer run of this module checks that no lookup reads
+    outside its table)."""
+    lib = L.lib
+    G = 1 << 30
+    x, y, z, out, ws, A = FAKE, FAKE + G, FAKE + 2 * G, FAKE + 3 * G, FAKE + 4 * G, FAKE + 8 * G
+    sz = ctypes.c_size_t(0)
+    cfg = L.Config()
+    calls = {
+        "copy": lambda t, a, o: lib.bwla_copy(t, 10, y, x, None),
+        "axpby": lambda t, a, o: lib.bwla_axpby(t, 10, 1.0, None, y, 1.0, None, z, x, None),
+        "dot": lambda t, a, o: lib.bwla_dot(t, a, 10, x, y, o, out, ws, G, None),
+        "nrm2": lambda t, a, o: lib.bwla_nrm2(t, a, 10, x, o, out, ws, G, None),
+        "dot_noalloc": lambda t, a, o: lib.bwla_dot_noalloc(t, a, 10, x, y, o, out, None),
+        "dot_strided": lambda t, a, o: lib.bwla_dot_strided(t, a, 10, x, 2, y, 3, o, out, ws, G, None),
+        "nrm2_strided": lambda t, a, o: lib.bwla_nrm2_strided(t, a, 10, x, 2, o, out, ws, G, None),
+        "asum": lambda t, a, o: lib.bwla_asum(t, a, 10, x, 2, o, out, ws, G, None),
+        "copy_strided": lambda t, a, o: lib.bwla_copy_strided(t, 10, y, 2, x, 3, None),
+        "axpby_strided": lambda t, a, o: lib.bwla_axpby_strided(t, 10, 1.0, None, y, 2, 1.0, None, z, 2, x, 3,
+                                                                None),
+        "scal": lambda t, a, o: lib.bwla_scal(t, 10, 2.0, None, x, 2, None),
+        "scal_to": lambda t, a, o: lib.bwla_scal_to(t, 10, 2.0, None, y, x, None),
+        "gemv": lambda t, a, o: lib.bwla_gemv(t, a, 0, 0, 8, 8, A, 8, x, o, y, ws, G, None),
+        "gemv_dot": lambda t, a, o: lib.bwla_gemv_dot(t, a, 0, 0, 8, 8, A, 8, x, y, z, o, out, ws, G, None),
+        "gemv_dot_ws": lambda t, a, o: lib.bwla_gemv_dot_workspace_size(t, 0, 0, 8, 8, ctypes.byref(sz)),
+        "gemv_ex": lambda t, a, o: lib.bwla_gemv_ex(t, a, 0, 0, 8, 8, 1.0, A, 8, x, 2, 0.5, o, y, 2, ws, G, None),
+        "gemv_ex_ws": lambda t, a, o: lib.bwla_gemv_ex_workspace_size(t, o, 0, 0, 8, 8, ctypes.byref(sz)),
+        "ger": lambda t, a, o: lib.bwla_ger(t, 0, 8, 8, x, y, A, 8, None),
+        "cg_update": lambda t, a, o: lib.bwla_cg_update(t, a, 10, 1.0, None, x, y, z, A, o, out, ws, G, None),
+        "workspace_size": lambda t, a, o: lib.bwla_workspace_size(L.OP_DOT, t, a, 0, 0, 1, 1000, ctypes.byref(sz)),
+        "get_config": lambda t, a, o: lib.bwla_get_config(L.OP_DOT, t, a, 1, 1000, ctypes.byref(cfg)),
+    }
+    with_acc = {"dot", "nrm2", "dot_noalloc", "dot_strided", "nrm2_strided", "asum", "gemv", "gemv_dot",
+                "gemv_ex", "cg_update", "workspace_size", "get_config"}
+    with_out = {"dot", "nrm2", "dot_noalloc", "dot_strided", "nrm2_strided", "asum", "gemv", "gemv_dot",
+                "gemv_ex", "gemv_ex_ws", "cg_update"}
+    for name, call in calls.items():
+        for bad in (3, 7, 99, -1, 2 ** 31 - 1):
+            assert call(bad, 0, 0) == L.ERR_UNSUPPORTED, (name, "dtype", bad)
+            if name in with_acc:
+                assert call(0, bad, 0) == L.ERR_UNSUPPORTED, (name, "acc", bad)
+            if name in with_out:
+                assert call(0, 0, bad) in (L.ERR_UNSUPPORTED, L.ERR_INVALID_ARG), (name, "out type", bad)
+    for bad in (-2, 8, 99):
+        assert lib.bwla_get_config(bad, 0, 0, 1, 1000, ctypes.byref(cfg)) == L.ERR_INVALID_ARG
+        assert lib.bwla_set_config(bad, 0, 0, 1, None) == L.ERR_INVALID_ARG
+    for bad in (3, 7, -1):
+        assert lib.bwla_set_config(L.OP_DOT, bad, 0, 1, None) == L.ERR_UNSUPPORTED
+
+
 def test_vector_validation(L):
     lib = L.lib
     assert lib.bwla_copy(0, -1, FAKE, FAKE + 4096, None) == L.ERR_INVALID_ARG
