@@ -40,6 +40,30 @@ bwla_status hip_check(hipError_t e, const char *what)
     return fail(BWLA_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// BWLA_LOG set to anything but "" or "0": every call that launches kernels
+// writes one line to stderr with the entry point, storage type, accumulation
+// mode, shape and the configuration it resolved (bwla_config's fields; grid
+// is the number of work-groups launched).
+bool log_enabled()
+{
+    static const bool on = [] {
+        const char *v = getenv("BWLA_LOG");
+        return v && v[0] && strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+void log_call(const char *what, int t, int acc, int64_t m, int64_t n, const Cfg &c)
+{
+    if (!log_enabled())
+        return;
+    static const char *const tname[3] = {"f64", "f32", "bf16"};
+    fprintf(stderr,
+            "bwla: %s %s %s m=%lld n=%lld block=%d vec=%d unroll=%d grid=%d increment=%d rows=%d split=%d\n",
+            what, tname[t], acc < 0 ? "-" : acc == BWLA_ACC_COMPENSATED ? "compensated" : "plain", (long long)m,
+            (long long)n, c.block, c.vec, c.unroll, c.grid, c.inc, c.rows, c.split);
+}
+
 bool valid_dtype(int t) { return t == BWLA_F64 || t == BWLA_F32 || t == BWLA_BF16; }
 size_t dsize(int t) { return t == BWLA_F64 ? 8 : (t == BWLA_F32 ? 4 : 2); }
 int native_vec(int t) { return (int)(16 / dsize(t)); }
@@ -420,6 +444,11 @@ int strided_grid(int64_t n, bool reduction)
     const int64_t cap = (int64_t)(reduction ? 2 : 8) * device_cus(); // reductions: few partials
     return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), per), cap));
 }
+// The fixed shape of the increment kernels, for the log.
+Cfg strided_cfg(int64_t n, bool reduction)
+{
+    return Cfg{kStridedBlock, 1, kStridedUnroll, strided_grid(n, reduction), 0, 1, 1};
+}
 size_t ws_strided(int64_t n)
 {
     const int g = strided_grid(n, true);
@@ -466,6 +495,7 @@ bwla_status bwla_copy(bwla_dtype t, int64_t n, const void *y, void *x, void *str
     if (overlaps(sx, sy))
         return fail(BWLA_ERR_INVALID_ARG, "x partially overlaps y");
     Cfg c = resolve_vector(BWLA_OP_COPY, t, BWLA_ACC_PLAIN, n, {x, y}, 2);
+    log_call("copy", t, -1, 1, n, c);
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         return launch_copy<T>(n, y, x, c, (hipStream_t)stream);
@@ -493,6 +523,7 @@ bwla_status bwla_axpby(bwla_dtype t, int64_t n, double alpha, const void *alpha_
     if ((alpha_dev && overlaps(sxa, span(alpha_dev, cs))) || (beta_dev && overlaps(sxa, span(beta_dev, cs))))
         return fail(BWLA_ERR_INVALID_ARG, "a device scalar lies inside the output x");
     Cfg c = resolve_vector(BWLA_OP_AXPBY, t, BWLA_ACC_PLAIN, n, {x, y, z}, 3);
+    log_call("axpby", t, -1, 1, n, c);
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         return launch_axpby<T>(n, alpha, alpha_dev, y, beta, beta_dev, z, x, c, (hipStream_t)stream);
@@ -559,6 +590,11 @@ static bwla_status reduce_launch(const RedPlan &plan, bwla_dtype t, bwla_acc acc
         return hip_check(launch_fill_zero(out, 1, out_t == BWLA_F64, s), "fill launch");
     const bool comp = acc == BWLA_ACC_COMPENSATED;
     const int of64 = out_t == BWLA_F64;
+    if (log_enabled()) {
+        const char *what = mode == kRedDot ? (plan.packed ? "dot" : "dot strided")
+                           : mode == kRedSq ? (plan.packed ? "nrm2" : "nrm2 strided") : "asum";
+        log_call(what, t, acc, 1, n, plan.packed ? plan.c : strided_cfg(n, true));
+    }
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         if (plan.packed)
@@ -679,6 +715,7 @@ bwla_status bwla_copy_strided(bwla_dtype t, int64_t n, const void *y, int64_t in
         return BWLA_OK;
     if (!sdisjoint(x, incx, y, incy, n, es))
         return fail(BWLA_ERR_INVALID_ARG, "x overlaps y");
+    log_call("copy strided", t, -1, 1, n, strided_cfg(n, false));
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         return launch_strided_elem<T>(kElemCopy, n, 0.0, nullptr, 0.0, nullptr, y, incy, nullptr, 0, x, incx,
@@ -714,6 +751,7 @@ bwla_status bwla_axpby_strided(bwla_dtype t, int64_t n, double alpha, const void
     Span sx = sspan(x, n, incx, es);
     if ((alpha_dev && overlaps(sx, span(alpha_dev, cs))) || (beta_dev && overlaps(sx, span(beta_dev, cs))))
         return fail(BWLA_ERR_INVALID_ARG, "a device scalar lies inside the output x");
+    log_call("axpby strided", t, -1, 1, n, strided_cfg(n, false));
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         return launch_strided_elem<T>(kElemAxpby, n, alpha, alpha_dev, beta, beta_dev, y, incy, z, incz, x, incx,
@@ -741,10 +779,13 @@ bwla_status bwla_scal(bwla_dtype t, int64_t n, double alpha, const void *alpha_d
     if (alpha_dev && overlaps(sspan(x, n, incx, es), span(alpha_dev, t == BWLA_F64 ? 8 : 4)))
         return fail(BWLA_ERR_INVALID_ARG, "the device scalar lies inside x");
     hipStream_t s = (hipStream_t)stream;
+    // unit increment: one read and one write stream, as the copy (its table entry)
+    const Cfg c = incx == 1 ? resolve_vector(BWLA_OP_COPY, t, BWLA_ACC_PLAIN, n, {x}, 2) : strided_cfg(n, false);
+    log_call(incx == 1 ? "scal" : "scal strided", t, -1, 1, n, c);
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
-        if (incx == 1) // reads and writes one stream each, as the copy
-            return launch_scal<T>(n, alpha, alpha_dev, x, x, resolve_vector(BWLA_OP_COPY, t, BWLA_ACC_PLAIN, n, {x}, 2), s);
+        if (incx == 1)
+            return launch_scal<T>(n, alpha, alpha_dev, x, x, c, s);
         return launch_strided_elem<T>(kElemScal, n, alpha, alpha_dev, 0.0, nullptr, x, incx, nullptr, 0, x, incx,
                                       strided_grid(n, false), s);
     });
@@ -770,6 +811,7 @@ bwla_status bwla_scal_to(bwla_dtype t, int64_t n, double alpha, const void *alph
         return fail(BWLA_ERR_INVALID_ARG, "the device scalar lies inside x");
     // one read stream and one write stream, as the copy: its table entry
     Cfg c = resolve_vector(BWLA_OP_COPY, t, BWLA_ACC_PLAIN, n, {x, y}, 2);
+    log_call("scal_to", t, -1, 1, n, c);
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         return launch_scal<T>(n, alpha, alpha_dev, y, x, c, (hipStream_t)stream);
@@ -881,6 +923,9 @@ static bwla_status gemv_common(bwla_dtype t, bwla_acc acc, bwla_layout layout, i
     const size_t need = gemv_ws(g, c, fused, &off);
     if (need && (!ws || ws_bytes < need))
         return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    // the shape logged is the kernel's: g.L lines of g.K contiguous elements
+    log_call(fused ? (g.rows ? "gemv_dot rows" : "gemv_dot cols") : (g.rows ? "gemv rows" : "gemv cols"), t, acc,
+             g.L, g.K, c);
     const void *wv = fused ? w : nullptr;
     hipError_t e = by_type(t, [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
@@ -992,6 +1037,8 @@ bwla_status bwla_gemv_ex(bwla_dtype t, bwla_acc acc, bwla_layout layout, int tra
     }
     if (!ws || ws_bytes < need)
         return fail(BWLA_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if (g.in_len > 0)
+        log_call(g.rows ? "gemv_ex rows" : "gemv_ex cols", t, acc, g.L, g.K, c);
     hipStream_t s = (hipStream_t)stream;
     void *tmp = (char *)ws + off_tmp;
     void *gws = (char *)ws + off_g;
@@ -1095,10 +1142,14 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha, 
                            void *x, const void *p, void *r, const void *q, bwla_dtype out_t, void *out,
                            void *ws, size_t ws_bytes, void *stream)
 {
+    // dtype, mode, n and the output first: the configuration lookup indexes
+    // its table by dtype
+    bwla_status st = check_reduction(t, acc, n, out_t, out, nullptr, 0, 0);
+    if (st)
+        return st;
     Cfg c = resolve_vector(kOpCg, t, acc, n, {x, p, r, q}, 6);
     const size_t need = n > 0 ? ws_dot(c) : 0;
-    bwla_status st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need);
-    if (st)
+    if ((st = check_reduction(t, acc, n, out_t, out, ws, ws_bytes, need)))
         return st;
     if (n == 0)
         return hip_check(launch_fill_zero(out, 1, out_t == BWLA_F64, (hipStream_t)stream), "fill launch");
