@@ -48,3 +48,39 @@ def mat(m, n, dtype, stream, layout="row", seed=0, dist="uniform", pad=0):
 def host(t, dtype=None):
     dtype = dtype or PREC[t.dtype]
     return W.from_torch(t, dtype)
+
+
+# Guard slack around outputs: the output lives inside a larger buffer whose
+# GUARD_BYTES before and after hold a NaN bit pattern no kernel computes; the
+# test checks after the call that every slack entry still holds it, which
+# catches stores past either end of the output (tail handling, split slices).
+GUARD_BYTES = 4096
+_SENTINEL = {torch.float64: (torch.int64, 0x7FF4DEADBEEF0001), torch.float32: (torch.int32, 0x7FA0DEAD),
+             torch.bfloat16: (torch.int16, 0x7FA5)}
+
+
+def guarded(n, dtype, offset=0):
+    """(view, check): an output of n entries of ``dtype`` (torch dtype or a
+    short name), ``offset`` entries past an aligned start, with sentinel
+    slack on both sides; check() asserts the slack is untouched."""
+    dt = DT.get(dtype, dtype)
+    it, bits = _SENTINEL[dt]
+    g = GUARD_BYTES // torch.empty(0, dtype=dt).element_size()
+    buf = torch.full((n + offset + 2 * g,), bits, dtype=it, device="cuda")
+    view = buf.view(dt)[g + offset:g + offset + n]
+    if n == 0:
+        view = view.reshape(0)
+
+    def check(what=""):
+        h = buf.cpu()
+        lo = int((h[:g + offset] != bits).sum())
+        hi = int((h[g + offset + n:] != bits).sum())
+        assert lo == 0 and hi == 0, "%s: %d guard entries before and %d after the output were written" % (
+            what, lo, hi)
+    return view, check
+
+
+def guarded_scalar(dtype):
+    """A 0-dim guarded output (for the reductions)."""
+    v, check = guarded(1, dtype)
+    return v.view(()), check

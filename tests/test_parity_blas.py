@@ -15,7 +15,7 @@ import torch
 
 import oracle
 from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector, cond_scale, plain_reduced
-from tests.gpu_util import DT, host, mat, need_gpu, vec
+from tests.gpu_util import DT, guarded, host, mat, need_gpu, vec
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +53,15 @@ def _buf(n, inc, dtype, stream):
     return vec(length, dtype, stream)
 
 
+def _out_buf(n, inc, dtype, stream):
+    """As _buf, for an output: the buffer sits between sentinel slack;
+    returns (tensor, f64 values, guard check)."""
+    t, t64 = _buf(n, inc, dtype, stream)
+    out, guard = guarded(t.numel(), dtype)
+    out.copy_(t)
+    return out, t64, guard
+
+
 def _ws(nbytes):
     from paper_1409_0669_amd import ops
     return ops._ws_ptr(ops.workspace(nbytes, torch.device("cuda")))
@@ -74,10 +83,11 @@ def _red_ws(dtype, n):
 def test_copy_strided_bitwise(dtype, n, incs):
     incy, incx = incs
     y, y64 = _buf(n, incy, dtype, 61)
-    x, x64 = _buf(n, incx, dtype, 62)
+    x, x64, guard = _out_buf(n, incx, dtype, 62)
     _check(_lib().lib.bwla_copy_strided(CODE[dtype], n, y.data_ptr(), incy, x.data_ptr(), incx, _stream()))
     ref = oracle.scatter(x64, oracle.copy(oracle.strided(y64, n, incy)), incx)
     assert bitwise_equal(host(x), ref)  # every entry, the gaps included
+    guard("copy_strided")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
@@ -87,13 +97,14 @@ def test_axpby_strided_bitwise(dtype, n, incs):
     incy, incz, incx = incs
     y, y64 = _buf(n, incy, dtype, 63)
     z, z64 = _buf(n, incz, dtype, 64)
-    x, x64 = _buf(n, incx, dtype, 65)
+    x, x64, guard = _out_buf(n, incx, dtype, 65)
     a, b = 0.75, -1.3
     _check(_lib().lib.bwla_axpby_strided(CODE[dtype], n, a, None, y.data_ptr(), incy, b, None, z.data_ptr(), incz,
                                          x.data_ptr(), incx, _stream()))
     vals = oracle.axpby(dtype, oracle.scalar(dtype, a), oracle.strided(y64, n, incy), oracle.scalar(dtype, b),
                         oracle.strided(z64, n, incz))
     assert bitwise_equal(host(x), oracle.scatter(x64, vals, incx))
+    guard("axpby_strided")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
@@ -116,10 +127,11 @@ def test_axpby_strided_in_place_and_device_scalars(dtype):
 @pytest.mark.parametrize("n", [1, 9, 4099, 1 << 20])
 @pytest.mark.parametrize("inc", [1, 2, -3])
 def test_scal_bitwise(dtype, n, inc):
-    x, x64 = _buf(n, inc, dtype, 68)
+    x, x64, guard = _out_buf(n, inc, dtype, 68)
     _check(_lib().lib.bwla_scal(CODE[dtype], n, -2.5, None, x.data_ptr(), inc, _stream()))
     vals = oracle.scal(dtype, oracle.scalar(dtype, -2.5), oracle.strided(x64, n, inc))
     assert bitwise_equal(host(x), oracle.scatter(x64, vals, inc))
+    guard("scal")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -142,12 +154,14 @@ def test_scal_to_bitwise(dtype, n):
     element; y untouched."""
     from paper_1409_0669_amd import ops
     y, y64 = vec(n, dtype, 83)
-    x = ops.scal_to(-2.5, y)
+    x, guard = guarded(n, dtype)
+    ops.scal_to(-2.5, y, out=x)
     assert bitwise_equal(host(x), oracle.scal(dtype, oracle.scalar(dtype, -2.5), y64))
     zb = torch.tensor([0.37], dtype=torch.float64 if dtype == "f64" else torch.float32, device="cuda")
     ops.scal_to(1.0, y, out=x, alpha_dev=zb)
     assert bitwise_equal(host(x), oracle.scal(dtype, oracle.scalar(dtype, 1.0, float(zb.item())), y64))
     assert bitwise_equal(host(y), y64)
+    guard("scal_to")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
@@ -273,7 +287,8 @@ def test_gemv_ex(dtype, layout, trans, case):
     _check(L.lib.bwla_gemv_ex_workspace_size(CODE[dtype], CODE[od], lay, trans, m, n, ctypes.byref(nbytes)))
     ws, wsn = _ws(nbytes.value)
     for acc in (0, 1):
-        yy = y.clone()
+        yy, guard = guarded(y.numel(), od)
+        yy.copy_(y)
         _check(L.lib.bwla_gemv_ex(CODE[dtype], acc, lay, trans, m, n, alpha, A.data_ptr(), lda, x.data_ptr(), incx,
                                   beta, CODE[od], yy.data_ptr(), incy, ws, wsn, _stream()))
         B = A64.T if trans else A64
@@ -289,6 +304,7 @@ def test_gemv_ex(dtype, layout, trans, case):
         mask = np.ones(got.size, bool)
         mask[oracle._positions(out_len, incy)] = False
         assert bitwise_equal(got[mask], y64[mask])
+        guard("gemv_ex case %d acc %d" % (case, acc))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

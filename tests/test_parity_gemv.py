@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from tests.criteria import TOL, bitwise_equal, check_vector, plain_reduced
-from tests.gpu_util import DT, host, mat, need_gpu, vec
+from tests.gpu_util import DT, guarded, host, mat, need_gpu, vec
 
 pytestmark = pytest.mark.gpu
 
@@ -42,10 +42,12 @@ def test_gemv(dtype, layout, trans, shape):
     A, A64 = mat(m, n, dtype, 21, layout=layout)
     x, x64 = vec(m if trans else n, dtype, 22)
     for acc in ("plain", "compensated"):
-        y = ops.gemv(A, x, trans=bool(trans), acc=acc)
+        y, guard = guarded(n if trans else m, ops.default_out_dtype(DT[dtype]))
+        ops.gemv(A, x, trans=bool(trans), acc=acc, out=y)
         ref, scale = _ref(A64, x64, trans)
-        check_vector(host(y), ref, scale, TOL[dtype], "%s %s t=%d %s" % (dtype, layout, trans, acc),
-                     plain_f32=plain_reduced(dtype, acc))
+        what = "%s %s t=%d %s" % (dtype, layout, trans, acc)
+        check_vector(host(y), ref, scale, TOL[dtype], what, plain_f32=plain_reduced(dtype, acc))
+        guard(what)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -121,10 +123,12 @@ def test_gemv_configs(dtype, cfg):
             for trans in (0, 1):
                 x, x64 = vec(m if trans else n, dtype, 27)
                 for acc in ("plain", "compensated"):
-                    y = ops.gemv(A, x, trans=bool(trans), acc=acc)
+                    y, guard = guarded(n if trans else m, ops.default_out_dtype(DT[dtype]))
+                    ops.gemv(A, x, trans=bool(trans), acc=acc, out=y)
                     ref, scale = _ref(A64, x64, trans)
-                    check_vector(host(y), ref, scale, TOL[dtype], "%s %s %s %s" % (cfg, layout, trans, acc),
-                                 plain_f32=plain_reduced(dtype, acc))
+                    what = "%s %s %s %s" % (cfg, layout, trans, acc)
+                    check_vector(host(y), ref, scale, TOL[dtype], what, plain_f32=plain_reduced(dtype, acc))
+                    guard(what)
 
 
 @pytest.mark.parametrize("acc", ["plain", "compensated"])

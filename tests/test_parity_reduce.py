@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from tests.criteria import TOL, check_scalar, cond_scale
-from tests.gpu_util import DT, need_gpu, vec
+from tests.gpu_util import DT, guarded_scalar, need_gpu, vec
 
 pytestmark = pytest.mark.gpu
 
@@ -107,11 +107,18 @@ def test_dot_configs(dtype, acc, cfg):
     for n in (3, 4099, 300017):
         x, x64 = vec(n, dtype, 13)
         y, y64 = vec(n, dtype, 14)
-        got = float(ops.dot(x, y, acc=acc).item())
+        od = ops.compute_dtype(DT[dtype])
+        out, guard = guarded_scalar(od)
+        got = float(ops.dot(x, y, acc=acc, out=out).item())
         check_scalar(got, oracle.dot(x64, y64), cond_scale(dtype, acc, np.abs(x64 * y64).sum()), TOL[dtype],
                      str(CONFIGS[cfg]))
-        check_scalar(float(ops.nrm2(x, acc=acc).item()), oracle.nrm2(x64), 0.0, TOL[dtype], "nrm2")
-        check_scalar(float(ops.asum(x, acc=acc).item()), oracle.asum(x64), 0.0, TOL[dtype], "asum")
+        guard("dot %d %s" % (n, CONFIGS[cfg]))
+        out, guard = guarded_scalar(od)
+        check_scalar(float(ops.nrm2(x, acc=acc, out=out).item()), oracle.nrm2(x64), 0.0, TOL[dtype], "nrm2")
+        guard("nrm2 %d %s" % (n, CONFIGS[cfg]))
+        out, guard = guarded_scalar(od)
+        check_scalar(float(ops.asum(x, acc=acc, out=out).item()), oracle.asum(x64), 0.0, TOL[dtype], "asum")
+        guard("asum %d %s" % (n, CONFIGS[cfg]))
 
 
 @pytest.mark.parametrize("dtype", DTYPES)

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 from tests.criteria import bitwise_equal
-from tests.gpu_util import DT, host, need_gpu, vec
+from tests.gpu_util import DT, guarded, host, need_gpu, vec
 
 pytestmark = pytest.mark.gpu
 
@@ -32,8 +32,10 @@ def _gpu():
 def test_copy_bitwise(dtype, n):
     from paper_1409_0669_amd import ops
     y, y64 = vec(n, dtype, 1)
-    x = ops.copy(y)
+    x, guard = guarded(n, dtype)
+    ops.copy(y, out=x)
     assert bitwise_equal(host(x), oracle.copy(y64))
+    guard("copy")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -42,9 +44,11 @@ def test_axpby_bitwise(dtype, n):
     from paper_1409_0669_amd import ops
     y, y64 = vec(n, dtype, 1)
     z, z64 = vec(n, dtype, 2)
-    x = ops.axpby(ALPHA, y, BETA, z)
+    x, guard = guarded(n, dtype)
+    ops.axpby(ALPHA, y, BETA, z, out=x)
     ref = oracle.axpby(dtype, oracle.scalar(dtype, ALPHA), y64, oracle.scalar(dtype, BETA), z64)
     assert bitwise_equal(host(x), ref)
+    guard("axpby")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -54,10 +58,11 @@ def test_axpby_misaligned(dtype, offsets):
     n = 10007
     y, y64 = vec(n, dtype, 3, pad_front=offsets[0])
     z, z64 = vec(n, dtype, 4, pad_front=offsets[1])
-    out = torch.empty(n + offsets[2], dtype=DT[dtype], device="cuda")[offsets[2]:]
+    out, guard = guarded(n, dtype, offset=offsets[2])
     ops.axpby(ALPHA, y, BETA, z, out=out)
     ref = oracle.axpby(dtype, oracle.scalar(dtype, ALPHA), y64, oracle.scalar(dtype, BETA), z64)
     assert bitwise_equal(host(out), ref)
+    guard("misaligned axpby")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -100,10 +105,15 @@ def test_stream_configs_bitwise(dtype, cfg):
     for n in (5, 4099, 300017):
         y, y64 = vec(n, dtype, 7)
         z, z64 = vec(n, dtype, 8)
-        x = ops.axpby(ALPHA, y, BETA, z)
+        x, guard = guarded(n, dtype)
+        ops.axpby(ALPHA, y, BETA, z, out=x)
         ref = oracle.axpby(dtype, oracle.scalar(dtype, ALPHA), y64, oracle.scalar(dtype, BETA), z64)
         assert bitwise_equal(host(x), ref), (n, CONFIGS[cfg])
-        assert bitwise_equal(host(ops.copy(y)), y64)
+        guard("axpby %d %s" % (n, CONFIGS[cfg]))
+        c, guard = guarded(n, dtype)
+        ops.copy(y, out=c)
+        assert bitwise_equal(host(c), y64)
+        guard("copy %d %s" % (n, CONFIGS[cfg]))
 
 
 def test_axpby_empty_and_specials():
