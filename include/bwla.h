@@ -107,7 +107,9 @@ typedef enum BWLA_ENUM_INT {
  *         paper's vector data types); widths above 16 bytes are issued as
  *         several 16-byte loads
  * unroll: independent accesses in flight per thread per iteration: 1, 2, 4,
- *         or 8 (8 for DOT, NRM2 and GEMV_COLS; the streaming operations take 4)
+ *         8, 16 or 32 (the streaming operations take up to 4, DOT and NRM2 up
+ *         to 8; GEMV_COLS takes 16 and 32 while those lines hold at most 128
+ *         bytes of A per thread, and halves larger values until they do)
  * GEMV_ROWS work-groups are never larger than the packs of one slice of a
  * line (rounded up to 64 threads), whatever the table says.
  * grid:   number of work-groups (streaming and reductions).  For GEMV_ROWS

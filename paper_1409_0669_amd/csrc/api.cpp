@@ -157,8 +157,8 @@ bwla_status check_cfg(const bwla_config &c)
         return fail(BWLA_ERR_INVALID_ARG, "config: block %d is not a multiple of 64 in [64, 1024]", c.block);
     if (c.vec && !(is_pow2(c.vec) && c.vec <= 16))
         return fail(BWLA_ERR_INVALID_ARG, "config: vec %d not in {1,2,4,8,16}", c.vec);
-    if (c.unroll && !(c.unroll == 1 || c.unroll == 2 || c.unroll == 4 || c.unroll == 8))
-        return fail(BWLA_ERR_INVALID_ARG, "config: unroll %d not in {1,2,4,8}", c.unroll);
+    if (c.unroll && !(is_pow2(c.unroll) && c.unroll <= 32))
+        return fail(BWLA_ERR_INVALID_ARG, "config: unroll %d not in {1,2,4,8,16,32}", c.unroll);
     if (c.rows && !(is_pow2(c.rows) && c.rows <= 8))
         return fail(BWLA_ERR_INVALID_ARG, "config: rows %d not in {1,2,4,8}", c.rows);
     if (c.grid < 0 || c.split < 0)
@@ -188,6 +188,8 @@ Cfg resolve_vector(int op, int t, int acc, int64_t n, std::initializer_list<cons
     c.unroll = u.unroll ? u.unroll : (op == BWLA_OP_DOT || op == BWLA_OP_NRM2 ? 4 : 1);
     if (c.unroll > 4 && op != BWLA_OP_DOT && op != BWLA_OP_NRM2)
         c.unroll = 4; // eight packs in flight exist for the reductions (and the cols GEMV) only
+    if (c.unroll > 8)
+        c.unroll = 8; // sixteen and more: the cols GEMV only
     c.inc = u.increment;
     c.rows = 1;
     c.split = 1;
@@ -251,7 +253,9 @@ Cfg resolve_cols(int t, int acc, int64_t L, int64_t K, const void *A, int64_t ld
     Cfg c;
     c.block = u.block ? u.block : 512;
     c.vec = fit_vec(u.vec ? u.vec : native_vec(t), dsize(t), {A}, ld);
-    c.unroll = u.unroll ? u.unroll : 4; // lines in flight per wave: 1, 2, 4 or 8
+    c.unroll = u.unroll ? u.unroll : 4; // lines in flight per wave: 1 to 32
+    while (c.unroll > 8 && (size_t)c.unroll * c.vec * dsize(t) > kColsLoadBytes)
+        c.unroll /= 2; // more would spill: at most kColsLoadBytes of A in flight per lane
     c.inc = 0;
     c.rows = 1;
     const int64_t tiles = std::max<int64_t>(1, ceil_div(K, 64 * (int64_t)c.vec));

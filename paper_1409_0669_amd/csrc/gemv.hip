@@ -19,11 +19,11 @@
 // cols kernel: out[k] = sum_l A[l*ld + k] v[l].  A work-group owns a tile of
 //   64*V consecutive outputs (V per lane, so each wave access is 64*V
 //   contiguous elements) and one of `split` slices of the lines; its waves
-//   take interleaved lines of the slice, U lines in flight.  The slice of v is
-//   staged in LDS (converted to the compute precision) and read as a
-//   wave-uniform broadcast.  Per-wave partial sums are combined through LDS in
-//   wave order; with split > 1 the slices' partials are combined in slice
-//   order by a second kernel.
+//   take interleaved lines of the slice, U lines in flight (up to 32).  Each
+//   v[l] is one scalar load per wave, issued with the loads of its line, so
+//   the first loads of A start without a staging pass or a barrier.  Per-wave
+//   partial sums are combined through LDS in wave order; with split > 1 the
+//   slices' partials are combined in slice order by a second kernel.
 //
 // Dot epilogue (w != NULL): the caller also wants s = <w, y> over the
 // outputs, with y as stored (the storage type equals the compute type
@@ -150,8 +150,8 @@ __global__ __launch_bounds__(1024) void k_gemv_rows(int64_t L, int64_t K, const 
 
 template <typename T, int V, int U, bool COMP>
 __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const T *A, int64_t ld,
-                                                    const T *v, DD *partials, void *out, int out_f64,
-                                                    int split, const T *w, DD *dparts, int xchg)
+                                                    const T *__restrict__ v, DD *partials, void *out,
+                                                    int out_f64, int split, const T *w, DD *dparts, int xchg)
 {
     using C = compute_t<T>;
     constexpr bool EXACT = std::is_same<T, bf16_t>::value;
@@ -159,67 +159,64 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
     const int64_t blk = xcd_block();
     const int64_t tile = blk / split;
     const int s = (int)(blk - tile * split);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    // the wave index as a wave-uniform (scalar) value, so that every v[l]
+    // below is one scalar load shared by the wave
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t k0 = tile * TK + (int64_t)lane * V;
     const bool full = k0 + V <= K;
     const int64_t per = (L + split - 1) / split;
     const int64_t lb = (int64_t)s * per;
     const int64_t le = lb + per < L ? lb + per : L;
 
-    // One LDS buffer serves first as the staged slice of v and then as the
-    // exchange area of the cross-wave combine.
-    constexpr int kStageBytes = kColsStageLines * (int)sizeof(C);
-    constexpr int kRedBytes = TK * (int)sizeof(DD);
-    __shared__ __attribute__((aligned(16))) char smem[kStageBytes > kRedBytes ? kStageBytes : kRedBytes];
-    C *vs = reinterpret_cast<C *>(smem);
+    // LDS for the cross-wave combine (the hand-over path).
+    __shared__ __attribute__((aligned(16))) DD red[TK];
     Acc<C, COMP> acc[V];
 
-    for (int64_t t0 = lb; t0 < le; t0 += kColsStageLines) {
-        const int tn = (int)(le - t0 < kColsStageLines ? le - t0 : kColsStageLines);
-        __syncthreads();
-        for (int i = threadIdx.x; i < tn; i += blockDim.x)
-            vs[i] = widen(v[t0 + i]);
-        __syncthreads();
-        const T *base = A + t0 * ld + k0;
-        int j = wave;
-        if (full) {
-            for (; j + (U - 1) * nw < tn; j += U * nw) {
-                Pack<T, V> a[U];
+    // v[l] is read with the U lines' loads (no staging pass and no barrier
+    // before the first loads of A).
+    const T *vt = v + lb;
+    const T *base = A + lb * ld + k0;
+    const int64_t tn = le - lb;
+    int64_t j = wave;
+    if (full) {
+        for (; j + (int64_t)(U - 1) * nw < tn; j += (int64_t)U * nw) {
+            Pack<T, V> a[U];
+            C xv[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    a[u] = load_pack_nt<T, V>(base + (int64_t)(j + u * nw) * ld);
-                end_of_loads();
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const C xl = vs[j + u * nw];
-#pragma unroll
-                    for (int e = 0; e < V; ++e)
-                        acc[e].template add_prod<EXACT>(widen(a[u].v[e]), xl);
-                }
+            for (int u = 0; u < U; ++u) {
+                a[u] = load_pack_nt<T, V>(base + (j + (int64_t)u * nw) * ld);
+                xv[u] = widen(vt[j + (int64_t)u * nw]);
             }
-            for (; j < tn; j += nw) {
-                Pack<T, V> a = load_pack_nt<T, V>(base + (int64_t)j * ld);
-                const C xl = vs[j];
+            end_of_loads();
+#pragma unroll
+            for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int e = 0; e < V; ++e)
-                    acc[e].template add_prod<EXACT>(widen(a.v[e]), xl);
-            }
-        } else if (k0 < K) {
-            for (; j < tn; j += nw) {
-                const C xl = vs[j];
+                    acc[e].template add_prod<EXACT>(widen(a[u].v[e]), xv[u]);
+        }
+        for (; j < tn; j += nw) {
+            Pack<T, V> a = load_pack_nt<T, V>(base + j * ld);
+            const C xl = widen(vt[j]);
 #pragma unroll
-                for (int e = 0; e < V; ++e)
-                    if (k0 + e < K)
-                        acc[e].template add_prod<EXACT>(widen(base[(int64_t)j * ld + e]), xl);
-            }
+            for (int e = 0; e < V; ++e)
+                acc[e].template add_prod<EXACT>(widen(a.v[e]), xl);
+        }
+    } else if (k0 < K) {
+        for (; j < tn; j += nw) {
+            const C xl = widen(vt[j]);
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (k0 + e < K)
+                    acc[e].template add_prod<EXACT>(widen(base[j * ld + e]), xl);
         }
     }
 
     // Combine the waves' partial sums in wave order through LDS.  With xchg
     // the launch gave every wave but the first (nw - 1) * TK pairs of dynamic
     // LDS: all waves write at once and wave 0 adds them in wave order after
-    // one barrier.  Otherwise the waves hand over one at a time through the
-    // staging buffer.  Both orders of addition are the same.
+    // one barrier.  Otherwise the waves hand over one at a time through a
+    // buffer of one tile of pairs.  Both orders of addition are the same.
     DD d[V];
 #pragma unroll
     for (int e = 0; e < V; ++e)
@@ -237,8 +234,6 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
                 for (int e = 0; e < V; ++e)
                     d[e] = combine<COMP>(d[e], xs[(wv - 1) * TK + lane * V + e]);
     } else {
-        __syncthreads();
-        DD *red = reinterpret_cast<DD *>(smem);
         for (int wv = 1; wv < nw; ++wv) {
             if (wave == wv)
 #pragma unroll
@@ -280,7 +275,7 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
 // partials in slice order.  Consecutive outputs read consecutive partials.
 // With w (same element type as out), the work-group also reduces w_o * y_o
 // over its outputs into dparts[blockIdx.x].
-constexpr int kCombineBatch = 8;
+constexpr int kCombineBatch = 16;
 
 template <bool COMP>
 __global__ __launch_bounds__(256) void k_combine_lines(const DD *partials, int64_t outputs, int64_t G,
@@ -294,22 +289,24 @@ __global__ __launch_bounds__(256) void k_combine_lines(const DD *partials, int64
     if (live) {
         const int64_t g = o / G, r = o - g * G;
         const DD *p = partials + g * split * G + r;
-        // slice order as written, with kCombineBatch partials in flight at a
-        // time (one at a time, a split of 128 cost 32 us of load latency)
-        DD t = p[0];
-        int64_t q = 1;
-        for (; q + kCombineBatch <= split; q += kCombineBatch) {
+        // slice order as written, kCombineBatch partials in flight at a time:
+        // a split of s costs ceil(s / kCombineBatch) load round trips (one at
+        // a time, a split of 128 cost 32 us of load latency).  The last batch
+        // re-reads the last partial in its unused places (no branch between
+        // the loads) and adds only the first nb.
+        DD t = {0.0, 0.0};
+        for (int64_t q = 0; q < split; q += kCombineBatch) {
+            const int64_t nb = split - q < kCombineBatch ? split - q : kCombineBatch;
             DD v[kCombineBatch];
 #pragma unroll
             for (int b = 0; b < kCombineBatch; ++b)
-                v[b] = p[(q + b) * G];
+                v[b] = p[(q + (b < nb ? b : nb - 1)) * G];
             end_of_loads();
 #pragma unroll
             for (int b = 0; b < kCombineBatch; ++b)
-                t = combine<COMP>(t, v[b]);
+                if (b < nb)
+                    t = q + b == 0 ? v[0] : combine<COMP>(t, v[b]);
         }
-        for (; q < split; ++q)
-            t = combine<COMP>(t, p[q * G]);
         y = t.hi + t.lo;
         store_out(out, o, out_f64, y);
     }
@@ -383,27 +380,35 @@ hipError_t launch_gemv_cols(int64_t L, int64_t K, bool comp, const void *A, int6
 {
     DD *partials = (DD *)ws;
     DD *dparts = w ? (DD *)((char *)ws + dparts_offset) : nullptr;
-    // lines in flight per wave: 1, 2, 4 or 8
+    // lines in flight per wave: 1, 2, 4, 8, 16 or 32 (16 and 32 only within
+    // kColsLoadBytes per lane; the configuration resolution keeps to that)
     auto with_unroll_cols = [](int u, auto &&f) -> hipError_t {
-        if (u == 8)
-            return f(std::integral_constant<int, 8>{});
+        switch (u) {
+        case 32: return f(std::integral_constant<int, 32>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        }
         return with_unroll(u, f);
     };
     hipError_t e = with_vec(c.vec, [&](auto V) {
-        return with_unroll_cols(c.unroll, [&](auto U) {
-            return with_bool(comp, [&](auto CP) {
-                const int64_t tiles = (K + 64 * V.value - 1) / (64 * V.value);
-                // the one-barrier wave combine when its exchange area is small
-                // enough not to limit how many work-groups share a CU
-                const size_t xbytes = (size_t)(c.block / 64 - 1) * 64 * V.value * sizeof(DD);
-                const int xchg = xbytes > 0 && xbytes <= kColsXchgBytes;
-                hipLaunchKernelGGL((k_gemv_cols<T, V.value, U.value, CP.value>),
-                                   dim3((unsigned)(tiles * c.split)), dim3(c.block),
-                                   (unsigned)(xchg ? xbytes : 0), s, L, K, (const T *)A, ld,
-                                   (const T *)v, partials, out, out_f64, c.split, (const T *)w,
-                                   dparts, xchg);
-                return hipGetLastError();
-            });
+        return with_unroll_cols(c.unroll, [&](auto U) -> hipError_t {
+            if constexpr (U.value > 8 && (size_t)U.value * V.value * sizeof(T) > kColsLoadBytes) {
+                return hipErrorInvalidValue;
+            } else {
+                return with_bool(comp, [&](auto CP) {
+                    const int64_t tiles = (K + 64 * V.value - 1) / (64 * V.value);
+                    // the one-barrier wave combine when its exchange area is
+                    // small enough not to limit how many work-groups share a CU
+                    const size_t xbytes = (size_t)(c.block / 64 - 1) * 64 * V.value * sizeof(DD);
+                    const int xchg = xbytes > 0 && xbytes <= kColsXchgBytes;
+                    hipLaunchKernelGGL((k_gemv_cols<T, V.value, U.value, CP.value>),
+                                       dim3((unsigned)(tiles * c.split)), dim3(c.block),
+                                       (unsigned)(xchg ? xbytes : 0), s, L, K, (const T *)A, ld,
+                                       (const T *)v, partials, out, out_f64, c.split, (const T *)w,
+                                       dparts, xchg);
+                    return hipGetLastError();
+                });
+            }
         });
     });
     if (e == hipSuccess && c.split > 1)

@@ -15,8 +15,11 @@ struct Cfg {
 };
 
 // The workspace of a reduction holds its float64 partials (DD pairs).
-constexpr int kColsStageLines = 2048; // x entries staged in LDS per pass (cols kernel)
 constexpr size_t kColsXchgBytes = 32768; // largest dynamic LDS of the cols kernel's wave combine
+// The cols kernel keeps 16 or 32 lines in flight per wave only while the
+// bytes of A each lane holds in flight stay within this (32 VGPRs): beyond
+// it the loads would spill.  Up to 8 lines are always allowed.
+constexpr size_t kColsLoadBytes = 128;
 
 // Map a runtime value onto a compile-time constant for template dispatch.
 template <typename F> hipError_t with_vec(int v, F &&f)

@@ -309,10 +309,13 @@ def _rows_candidates(dtype, quick, cus=256):
 def _cols_candidates(dtype, quick, cus=256):
     # one element per lane included: with few outputs the cols kernel's
     # split (and its second kernel) grows with the pack width
-    native = 16 // torch.tensor([], dtype=dtype).element_size()
+    # 16 and 32 lines in flight only where the library takes them (at most 128
+    # bytes of A per lane in flight)
+    es = torch.tensor([], dtype=dtype).element_size()
+    native = 16 // es
     vecs = (native,) if quick else tuple(sorted({1, max(1, native // 2), native}))
     return [dict(block=b, vec=v, unroll=u, split=0, grid=g * cus) for b in (256, 512, 1024) for v in vecs
-            for u in (2, 4, 8) for g in GEMV_GROUPS_PER_CU]
+            for u in (2, 4, 8, 16, 32) if u <= 8 or u * v * es <= 128 for g in GEMV_GROUPS_PER_CU]
 
 
 # GEMV shapes tuned; each size class is tuned on every shape that falls in it

@@ -98,6 +98,29 @@ def test_unknown_enum_values_are_rejected(L):
         assert lib.bwla_set_config(L.OP_DOT, bad, 0, 1, None) == L.ERR_UNSUPPORTED
 
 
+def test_unroll_limits(L):
+    """unroll takes 1..32 (powers of two); each operation keeps to what its
+    kernels have: the streaming operations 4, the reductions 8, the cols
+    GEMV 32 while those lines hold at most 128 bytes of A per lane."""
+    import torch
+    from paper_1409_0669_amd import ops
+    lib = L.lib
+    for bad in (3, 64, -1):
+        assert lib.bwla_set_config(L.OP_DOT, 0, -1, -1, ctypes.byref(L.Config(unroll=bad))) == L.ERR_INVALID_ARG
+    try:
+        for dt, vec, want in ((torch.float32, 1, 32), (torch.float32, 2, 16), (torch.float32, 4, 8),
+                              (torch.float64, 1, 16), (torch.float64, 2, 8), (torch.bfloat16, 2, 32),
+                              (torch.bfloat16, 8, 8)):
+            ops.set_config(L.OP_GEMV_COLS, dt, -1, block=1024, vec=vec, unroll=32)
+            assert ops.get_config(L.OP_GEMV_COLS, dt, 4096, 4096)["unroll"] == want, (dt, vec)
+        ops.set_config(L.OP_DOT, torch.float32, -1, unroll=32)
+        assert ops.get_config(L.OP_DOT, torch.float32, 0, 1 << 20)["unroll"] == 8
+        ops.set_config(L.OP_AXPBY, torch.float32, -1, unroll=16)
+        assert ops.get_config(L.OP_AXPBY, torch.float32, 0, 1 << 20)["unroll"] == 4
+    finally:
+        ops.reset_config()
+
+
 def test_vector_validation(L):
     lib = L.lib
     assert lib.bwla_copy(0, -1, FAKE, FAKE + 4096, None) == L.ERR_INVALID_ARG

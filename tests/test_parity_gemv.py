@@ -103,11 +103,15 @@ def test_gemv_empty():
 ROWS_CFG = [dict(block=64, vec=1, rows=1, split=1), dict(block=128, vec=2, rows=2, split=3, unroll=2),
             dict(block=256, vec=4, rows=8, split=1, unroll=2), dict(block=1024, vec=16, rows=4, split=2),
             dict(block=512, vec=8, rows=1, split=7, unroll=2),
-            dict(block=256, vec=4, rows=4, split=0, grid=1000, unroll=2), dict(block=128, vec=2, rows=8, grid=37)]
+            dict(block=256, vec=4, rows=4, split=0, grid=1000, unroll=2), dict(block=128, vec=2, rows=8, grid=37),
+            dict(block=512, vec=4, rows=2, split=0, unroll=2), dict(block=256, vec=1, rows=4, split=5)]
 COLS_CFG = [dict(block=64, vec=1, unroll=1, split=1), dict(block=128, vec=2, unroll=2, split=3),
             dict(block=256, vec=4, unroll=4, split=1), dict(block=1024, vec=16, unroll=4, split=2),
             dict(block=512, vec=8, unroll=1, split=9),
-            dict(block=256, vec=2, unroll=8, split=0, grid=700), dict(block=512, vec=4, unroll=2, grid=33)]
+            dict(block=256, vec=2, unroll=8, split=0, grid=700), dict(block=512, vec=4, unroll=2, grid=33),
+            # 32 and 16 lines in flight (halved where they would hold more
+            # than 128 bytes of A per lane)
+            dict(block=1024, vec=1, unroll=32, split=0, grid=256), dict(block=512, vec=2, unroll=16, split=3)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
