@@ -275,9 +275,9 @@ __global__ __launch_bounds__(1024) void k_gemv_cols(int64_t L, int64_t K, const 
 // partials in slice order.  Consecutive outputs read consecutive partials.
 // With w (same element type as out), the work-group also reduces w_o * y_o
 // over its outputs into dparts[blockIdx.x].
-constexpr int kCombineBatch = 16;
-
-template <bool COMP>
+// B partials in flight per round trip: the smallest power of two (2 to 16)
+// that holds the split, so a split of up to 16 is one round trip.
+template <bool COMP, int B>
 __global__ __launch_bounds__(256) void k_combine_lines(const DD *partials, int64_t outputs, int64_t G,
                                                        int64_t split, void *out, int out_f64,
                                                        const void *w, DD *dparts)
@@ -289,21 +289,21 @@ __global__ __launch_bounds__(256) void k_combine_lines(const DD *partials, int64
     if (live) {
         const int64_t g = o / G, r = o - g * G;
         const DD *p = partials + g * split * G + r;
-        // slice order as written, kCombineBatch partials in flight at a time:
-        // a split of s costs ceil(s / kCombineBatch) load round trips (one at
-        // a time, a split of 128 cost 32 us of load latency).  The last batch
-        // re-reads the last partial in its unused places (no branch between
-        // the loads) and adds only the first nb.
+        // slice order as written, B partials in flight at a time: a split of
+        // s costs ceil(s / B) load round trips (one at a time, a split of 128
+        // cost 32 us of load latency).  The last batch re-reads the last
+        // partial in its unused places (no branch between the loads) and
+        // adds only the first nb.
         DD t = {0.0, 0.0};
-        for (int64_t q = 0; q < split; q += kCombineBatch) {
-            const int64_t nb = split - q < kCombineBatch ? split - q : kCombineBatch;
-            DD v[kCombineBatch];
+        for (int64_t q = 0; q < split; q += B) {
+            const int64_t nb = split - q < B ? split - q : B;
+            DD v[B];
 #pragma unroll
-            for (int b = 0; b < kCombineBatch; ++b)
+            for (int b = 0; b < B; ++b)
                 v[b] = p[(q + (b < nb ? b : nb - 1)) * G];
             end_of_loads();
 #pragma unroll
-            for (int b = 0; b < kCombineBatch; ++b)
+            for (int b = 0; b < B; ++b)
                 if (b < nb)
                     t = q + b == 0 ? v[0] : combine<COMP>(t, v[b]);
         }
@@ -330,9 +330,18 @@ hipError_t launch_combine_lines(const void *partials, int64_t outputs, int64_t G
 {
     const int64_t blocks = (outputs + 255) / 256;
     return with_bool(comp, [&](auto CP) {
-        hipLaunchKernelGGL((k_combine_lines<CP.value>), dim3((unsigned)blocks), dim3(256), 0, s,
-                           (const DD *)partials, outputs, G, split, out, out_f64, w, (DD *)dparts);
-        return hipGetLastError();
+        auto go = [&](auto B) {
+            hipLaunchKernelGGL((k_combine_lines<CP.value, B.value>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               (const DD *)partials, outputs, G, split, out, out_f64, w, (DD *)dparts);
+            return hipGetLastError();
+        };
+        if (split <= 2)
+            return go(std::integral_constant<int, 2>{});
+        if (split <= 4)
+            return go(std::integral_constant<int, 4>{});
+        if (split <= 8)
+            return go(std::integral_constant<int, 8>{});
+        return go(std::integral_constant<int, 16>{});
     });
 }
 #endif

@@ -197,8 +197,8 @@ def trip_loads(kernel, args, es):
         return args[2] * (args[1] + 1) * lp(args[0])
     if kernel == "k_gemv_cols":    # <V, U, COMP>: U lines
         return args[1] * lp(args[0])
-    if kernel == "k_combine_lines":   # <COMP>: a batch of sixteen 16-byte partials
-        return 16
+    if kernel == "k_combine_lines":   # <COMP, B>: a batch of B 16-byte partials
+        return args[1]
     if kernel == "k_combine_scalar":  # <COMP>: a batch of eight 16-byte partials
         return 8
     return None
