@@ -114,6 +114,23 @@ def test_grouped_empty_problems():
     assert torch.all(y == 0)
 
 
+def test_capture_refuses_the_default_stream():
+    """A plan is recorded into a graph only on a created stream: the default
+    (null) stream gives BWLA_ERR_NOT_CAPTURABLE before anything is enqueued,
+    and the plan still runs afterwards."""
+    need_gpu()
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd.batch import BatchPlan
+    p = torch.ones(1000, dtype=torch.float32, device="cuda")
+    out = torch.zeros(1, device="cuda")
+    plan = BatchPlan([], [(p, p, out)])
+    assert L.lib.bwla_batch_capture(plan._h, None) == L.ERR_NOT_CAPTURABLE
+    assert "default stream" in L.lib.bwla_last_error().decode()
+    plan.run()
+    torch.cuda.synchronize()
+    assert float(out.item()) == 1000.0
+
+
 @pytest.mark.parametrize("dtype", ["bf16", "f32"])
 def test_grouped_full_workload_every_problem(dtype):
     """512 GEMVs with M, N log-uniform in [32, 4096] and 4096 dots with n
