@@ -50,6 +50,8 @@ def parse():
                     help="least time of the oracle's passes over the step (the naive loops take half of it "
                          "per thread count)")
     ap.add_argument("--tuning", default=None, help="tuning table to load before timing")
+    ap.add_argument("--accuracy-json", default=None,
+                    help="also write the accuracy object (every row's error against the oracle) to this file")
     ap.add_argument("--settle", type=float, default=5.0,
                     help="seconds to wait before touching the GPU: for a few seconds after a process that "
                          "used tens of GB of device memory exits (the GPU test suite), HBM-bound kernels "
@@ -1148,6 +1150,10 @@ def main():
         "accuracy": accuracy,
     }
     print(json.dumps(line), flush=True)
+    if args.accuracy_json and accuracy is not None:
+        with open(args.accuracy_json, "w") as f:
+            json.dump({"device": torch.cuda.get_device_name(), "date": time.strftime("%Y-%m-%d"),
+                       "command": "python bench.py --accuracy-json <file>", "accuracy": accuracy}, f, indent=1)
     del keep
 
 
