@@ -7,7 +7,7 @@ import torch
 import oracle
 import workloads as W
 from tests.criteria import TOL, check_scalar, check_vector, cond_scale, plain_reduced
-from tests.gpu_util import host
+from tests.gpu_util import guarded, host
 
 
 def problems(dtype, n_gemv, n_dot, gemv_hi, dot_hi, seed=0, align=64):
@@ -20,7 +20,10 @@ def problems(dtype, n_gemv, n_dot, gemv_hi, dot_hi, seed=0, align=64):
     return from_sizes(dtype, Ms, Ns, Ds, seed, align)
 
 
-def from_sizes(dtype, Ms, Ns, Ds, seed=0, align=64):
+def from_sizes(dtype, Ms, Ns, Ds, seed=0, align=64, guards=None):
+    """As problems(), from given sizes.  With a list ``guards``, every output
+    sits between sentinel slack (tests.gpu_util.guarded) and the list
+    receives each output's check."""
     def off(sizes):
         o, offs = 0, []
         for s in sizes:
@@ -40,12 +43,20 @@ def from_sizes(dtype, Ms, Ns, Ds, seed=0, align=64):
         m, n = int(m), int(n)
         Ai = A[a_off[i]:a_off[i] + m * n].view(m, n)
         xi = X[x_off[i]:x_off[i] + n]
-        gemvs.append((Ai, xi, torch.empty(m, dtype=od, device="cuda")))
+        gemvs.append((Ai, xi, _out(m, od, guards, "gemv %d" % i)))
     dots = []
     for i, n in enumerate(Ds):
         n = int(n)
-        dots.append((P[d_off[i]:d_off[i] + n], Q[d_off[i]:d_off[i] + n], torch.empty(1, dtype=od, device="cuda")))
+        dots.append((P[d_off[i]:d_off[i] + n], Q[d_off[i]:d_off[i] + n], _out(1, od, guards, "dot %d" % i)))
     return gemvs, dots
+
+
+def _out(n, od, guards, what):
+    if guards is None:
+        return torch.empty(n, dtype=od, device="cuda")
+    view, check = guarded(n, od)
+    guards.append(lambda: check(what))
+    return view
 
 
 def check(dtype, acc, gemvs, dots, gi=None, di=None):

@@ -1,7 +1,8 @@
 """Batched launch with one work-group per work item (the plans' default):
 every problem matches the oracle; results are bitwise independent of the batch
 order; graph replays equal the direct launch bitwise; a batch of one matches
-the single-problem call; empty problems; the full uneven workload (sampled)."""
+the single-problem call; empty problems; the full uneven workload, every
+problem; sentinel slack around the outputs stays untouched."""
 from __future__ import annotations
 
 import numpy as np
@@ -141,13 +142,16 @@ def test_grouped_full_workload_every_problem(dtype):
     need_gpu()
     from paper_1409_0669_amd.batch import BatchPlan
     M, N, D = W.batched_sizes(0)
-    gemvs, dots = from_sizes(dtype, M, N, D, seed=0)
+    guards = []
+    gemvs, dots = from_sizes(dtype, M, N, D, seed=0, guards=guards)
     plan = BatchPlan(gemvs, dots, acc="compensated")
     info = plan.info()
     assert info["items"] > 0
     plan.run()
     torch.cuda.synchronize()
     check(dtype, "compensated", gemvs, dots)
+    for g in guards:
+        g()
     y0 = [host(g[2]) for g in gemvs]
     d0 = [host(d[2]) for d in dots]
     s = torch.cuda.Stream()
@@ -179,10 +183,13 @@ def test_grouped_every_read_mode(dtype, align, block):
     Ms = np.array([1, 7, 33, 300, 5, 64, 3, 40])
     Ns = np.array([1, 3, 17, 1000, cap, cap + 2, cap + 8, 9001])
     Ds = np.array([0, 1, 9, 1000, 65536, 65537, 200003])
-    gemvs, dots = from_sizes(dtype, Ms, Ns, Ds, seed=3, align=align)
+    guards = []
+    gemvs, dots = from_sizes(dtype, Ms, Ns, Ds, seed=3, align=align, guards=guards)
     for acc in ("plain", "compensated"):
         plan = BatchPlan(gemvs, dots, acc=acc, block=block)
         plan.run()
         torch.cuda.synchronize()
         check(dtype, acc, gemvs, dots)
+        for g in guards:  # no store past any output
+            g()
         plan.close()
