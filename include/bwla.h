@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BWLA_ABI_VERSION 3
+#define BWLA_ABI_VERSION 4
 
 /* In C++ the enumerations below have int as their fixed underlying type, so
  * every int a caller passes is a value of the parameter's type and the library
@@ -90,7 +90,8 @@ typedef enum BWLA_ENUM_INT {
     BWLA_OP_GER = 5,
     BWLA_OP_NRM2 = 6,
     BWLA_OP_CG = 7,        /* the fused CG-style update */
-    BWLA_OP_COUNT = 8
+    BWLA_OP_BATCH = 8,     /* the batch plans (bwla_batch_plan_create) */
+    BWLA_OP_COUNT = 9
 } bwla_op;
 
 /* Kernel configuration: the paper's triple (kernel source, local work size,
@@ -102,6 +103,10 @@ typedef enum BWLA_ENUM_INT {
  *   GEMV_COLS:        block, vec, unroll (lines in flight), split (blocks across
  *                     lines), grid
  *   GER:              block, vec, rows
+ *   BATCH:            block (work-group size, at most 512), unroll (packs of a
+ *                     GEMV row each lane of a staged tile owns: sets how many
+ *                     lanes share a row); its size class is that of the plan's
+ *                     algorithmic bytes
  * block:  threads per work-group, a multiple of 64 in [64, 1024]
  * vec:    consecutive elements per thread per access: 1, 2, 4, 8 or 16 (the
  *         paper's vector data types); widths above 16 bytes are issued as
@@ -321,8 +326,12 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
  * capture: records the same kernels into a HIP graph owned by the plan.
  * replay: launches the captured graph.
  * Descriptor pointers must stay valid while the plan is used.
- * cfg (may be NULL) sets only the work-group size: cfg->block, a multiple
- * of 64 up to 512 (default 256); other fields are ignored.
+ * cfg (may be NULL) sets the work-group size (cfg->block, a multiple of 64
+ * up to 512) and the packs of a GEMV row each lane of a staged tile owns
+ * (cfg->unroll, a power of two up to 32); other fields are ignored.  A zero
+ * (or NULL) field takes the configuration table's BWLA_OP_BATCH entry for
+ * (t, acc, size class of the plan's algorithmic bytes), else the defaults
+ * (256 threads, 16 packs per lane).
  * (The library also holds a persistent work-queue form of this launch, a
  * machine-sized grid drawing items from an atomic counter.  It has not been
  * validated on hardware and is switched off: with
@@ -370,7 +379,8 @@ void bwla_batch_plan_destroy(bwla_batch_plan *p);
 bwla_status bwla_set_config(bwla_op op, bwla_dtype t, int acc, int size_class, const bwla_config *cfg);
 /* The configuration a call with this op, type, accumulation mode and shape
  * would use after defaults are resolved (m = lines, n = line length for
- * GEMV/GER; m ignored for vectors). */
+ * GEMV/GER; m ignored for vectors; for BATCH, n = the plan's algorithmic
+ * bytes and m ignored). */
 bwla_status bwla_get_config(bwla_op op, bwla_dtype t, bwla_acc acc, int64_t m, int64_t n, bwla_config *cfg);
 /* Load a tuning table written by the autotuner: text, one entry per line,
  * "op dtype acc size_class block vec unroll grid increment rows split" (acc

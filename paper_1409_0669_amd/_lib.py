@@ -20,9 +20,9 @@ F64, F32, BF16 = 0, 1, 2
 ROW_MAJOR, COL_MAJOR = 0, 1
 ACC_PLAIN, ACC_COMPENSATED = 0, 1
 INC_GLOBAL, INC_LOCAL = 0, 1
-OP_COPY, OP_AXPBY, OP_DOT, OP_GEMV_ROWS, OP_GEMV_COLS, OP_GER, OP_NRM2, OP_CG = range(8)
-OP_COUNT = 8
-ABI_VERSION = 3  # BWLA_ABI_VERSION of include/bwla.h
+OP_COPY, OP_AXPBY, OP_DOT, OP_GEMV_ROWS, OP_GEMV_COLS, OP_GER, OP_NRM2, OP_CG, OP_BATCH = range(9)
+OP_COUNT = 9
+ABI_VERSION = 4  # BWLA_ABI_VERSION of include/bwla.h
 
 STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "INVALID_ARG", ERR_UNSUPPORTED: "UNSUPPORTED",
                 ERR_WORKSPACE: "WORKSPACE", ERR_HIP: "HIP", ERR_NOT_CAPTURABLE: "NOT_CAPTURABLE"}

@@ -1,8 +1,10 @@
 """``BatchPlan``: many uneven row-major GEMVs and dots in one batched launch --
 one work-group per work item (row tiles of the GEMVs, chunks of the dots,
-largest first), a GEMV kernel and a dot kernel, then a finalize kernel that
-combines each dot's chunk partials in chunk order -- optionally captured in
-a HIP graph and replayed."""
+largest first), one kernel per kind of item (GEMV tiles with x staged in LDS,
+the other GEMV tiles, dot chunks), then a finalize kernel that combines each
+dot's chunk partials in chunk order -- optionally captured in a HIP graph and
+replayed.  The work-group size and the packs of a GEMV row each lane owns come
+from the tuning table's batch entry unless given."""
 from __future__ import annotations
 
 import ctypes
@@ -20,7 +22,7 @@ class BatchPlan:
     one-element ``out_dtype`` tensor.  All inputs share one storage dtype.
     The plan keeps references to every tensor it was given."""
 
-    def __init__(self, gemvs=(), dots=(), acc="plain", out_dtype=None, grid=0, block=0):
+    def __init__(self, gemvs=(), dots=(), acc="plain", out_dtype=None, grid=0, block=0, packs=0):
         gemvs, dots = list(gemvs), list(dots)
         first = gemvs[0][0] if gemvs else (dots[0][0] if dots else None)
         if first is None:
@@ -46,7 +48,9 @@ class BatchPlan:
             if out.dtype != self.out_dtype or out.numel() != 1:
                 raise BwlaError(L.ERR_INVALID_ARG, "dot %d: out must be one %s" % (i, self.out_dtype))
             d[i] = L.DotDesc(x.data_ptr(), y.data_ptr(), x.numel(), out.data_ptr())
-        cfg = L.Config(block=int(block), grid=int(grid))
+        # block (work-group size) and packs (packs of a GEMV row per lane of a
+        # staged tile): 0 takes the tuning table's batch entry
+        cfg = L.Config(block=int(block), grid=int(grid), unroll=int(packs))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(lib.bwla_batch_plan_create(ops.dtype_code(self.dtype), ops._ACC[acc],

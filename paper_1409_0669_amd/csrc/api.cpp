@@ -293,6 +293,22 @@ Cfg resolve_ger(int t, int64_t L, int64_t K, const void *a, const void *b, const
     return c;
 }
 
+// Batch plans: the work-group size and the packs of a GEMV row each lane of a
+// staged tile owns (in unroll), from the table entry of the plan's size class.
+Cfg resolve_batch(int t, int acc, double bytes)
+{
+    bwla_config u = lookup(BWLA_OP_BATCH, t, acc, bytes);
+    Cfg c{};
+    c.block = std::min(u.block ? u.block : 256, 512);
+    c.vec = native_vec(t);
+    c.unroll = u.unroll ? u.unroll : kStagedPacks;
+    c.grid = 0;
+    c.inc = 0;
+    c.rows = 1;
+    c.split = 1;
+    return c;
+}
+
 // Workspace = the float64 (DD) partials of the first stage.
 size_t ws_dot(const Cfg &c) { return c.grid > 1 ? (size_t)c.grid * sizeof(DD) : 0; }
 size_t ws_rows(const Cfg &c, int64_t L)
@@ -1275,6 +1291,7 @@ bwla_status bwla_get_config(bwla_op op, bwla_dtype t, bwla_acc acc, int64_t m, i
     case BWLA_OP_GEMV_ROWS: c = resolve_rows(t, acc, m, n, nullptr, 0, nullptr); break;
     case BWLA_OP_GEMV_COLS: c = resolve_cols(t, acc, m, n, nullptr, 0, nullptr); break;
     case BWLA_OP_GER: c = resolve_ger(t, m, n, nullptr, nullptr, nullptr, 0); break;
+    case BWLA_OP_BATCH: c = resolve_batch(t, acc, (double)n); break;
     default: return fail(BWLA_ERR_INVALID_ARG, "op %d", op);
     }
     cfg->block = c.block;
@@ -1440,12 +1457,21 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
                 aligned = false;
         }
     }
+    // the plan's algorithmic bytes select its table entry (a cfg field that
+    // is set overrides it)
+    double total = 0;
+    for (int i = 0; i < ng; ++i)
+        total += (double)g[i].m * g[i].n * es + (double)g[i].n * es + (double)g[i].m * os;
+    for (int i = 0; i < nd; ++i)
+        total += 2.0 * d[i].n * es + os;
+    const Cfg bc = resolve_batch(t, acc, total);
+    const int packs_per_lane = cfg && cfg->unroll ? cfg->unroll : bc.unroll;
     bwla_batch_plan *p = new bwla_batch_plan();
     p->t = t;
     p->acc = acc;
     p->out_t = out_t;
     p->vec = aligned ? nv : 1;
-    p->block = cfg && cfg->block ? cfg->block : 256;
+    p->block = cfg && cfg->block ? cfg->block : bc.block;
     p->persistent = false;
     (void)hipGetDevice(&p->device);
 
@@ -1487,8 +1513,8 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
             b.mode = p->vec == 1 ? kModeScalar : kModePacked;
         }
         int64_t packs = std::max<int64_t>(1, ceil_div(q.n, v_item));
-        if (b.mode == kModeStaged && !p->persistent) // each lane owns up to kStagedPacks packs of its row
-            packs = ceil_div(packs, kStagedPacks);
+        if (b.mode == kModeStaged && !p->persistent) // each lane owns up to packs_per_lane packs of its row
+            packs = ceil_div(packs, packs_per_lane);
         int lanes = 1;
         while (lanes < 64 && lanes < packs)
             lanes <<= 1;
@@ -1581,6 +1607,10 @@ bwla_status bwla_batch_plan_create(bwla_dtype t, bwla_acc acc, bwla_dtype out_t,
     } else {
         p->grid = (int)std::max<int64_t>(1, p->n_items); // one work-group per item
     }
+    // the shape logged: work items and the plan's algorithmic bytes; unroll
+    // is the packs per lane of the staged GEMV tiles
+    log_call("batch plan", t, acc, p->n_items, (int64_t)total,
+             Cfg{p->block, p->vec, packs_per_lane, p->grid, 0, 1, 1});
 
     auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
         if (bytes == 0)

@@ -142,7 +142,7 @@ def time_ms(fn, reps: int = 10, warmup: int = 2, batch: int = PIPELINE) -> float
 
 
 # operations whose table entries are kept per accumulation mode
-REDUCING = ("dot", "nrm2", "cg", "gemv")
+REDUCING = ("dot", "nrm2", "cg", "gemv", "batch")
 
 
 class Workload:
@@ -175,6 +175,29 @@ class Workload:
             self.v = W.device_draw(n, name, 0, 8)
             self.bytes = (m * n + m + n) * s
             self.table_op = L.OP_GER
+        elif op == "batch":  # the uneven batch: sizes (M[], N[], D[]) in `m`
+            from .batch import BatchPlan
+            Ms, Ns, Ds = m
+            od = ops.default_out_dtype(dtype)
+            A = W.device_draw(max(1, int(sum(int(a) * int(b) for a, b in zip(Ms, Ns)))), name, 0, 501)
+            X = W.device_draw(max(1, int(sum(int(b) for b in Ns))), name, 0, 502)
+            P = W.device_draw(max(1, int(sum(int(d) for d in Ds))), name, 0, 503)
+            Q = W.device_draw(max(1, int(sum(int(d) for d in Ds))), name, 0, 504)
+            self.gemvs, self.dots = [], []
+            oa = ox = 0
+            for a, b in zip(Ms, Ns):
+                a, b = int(a), int(b)
+                self.gemvs.append((A[oa:oa + a * b].view(a, b), X[ox:ox + b], torch.empty(a, dtype=od, device="cuda")))
+                oa, ox = oa + a * b, ox + b
+            op_ = 0
+            for d in Ds:
+                d = int(d)
+                self.dots.append((P[op_:op_ + d], Q[op_:op_ + d], torch.empty(1, dtype=od, device="cuda")))
+                op_ += d
+            self._plan_cls, self._plan, self._plan_cfg = BatchPlan, None, None
+            self.bytes = int(BatchPlan(self.gemvs, self.dots, acc=acc).info()["bytes"])
+            self.table_op = L.OP_BATCH
+            self.table_acc = acc
         else:  # gemv_rows / gemv_cols: y = A x with A m x n in the layout that selects the kernel
             A = W.device_draw(m * n, name, 0, 3).view(m, n)
             self.A = A if layout == "row" else A.t().contiguous().t()
@@ -199,6 +222,14 @@ class Workload:
             ops.cg_update(1e-9, self.x, self.y, self.r, self.z, acc=self.acc)
         elif o == "ger":
             ops.ger(self.u, self.v, self.A)
+        elif o == "batch":
+            # a plan reads its configuration when it is built: rebuild it when
+            # the table entry under test changes (in the untimed warm-up calls)
+            cfg = ops.get_config(L.OP_BATCH, self.dtype, 0, self.bytes, acc=self.acc)
+            if cfg != self._plan_cfg:
+                self._plan = self._plan_cls(self.gemvs, self.dots, acc=self.acc)
+                self._plan_cfg = cfg
+            self._plan.run()
         else:
             ops.gemv(self.A, self.x, acc=self.acc, out=self.yv)
 
@@ -372,28 +403,46 @@ def _ger_candidates(dtype, quick):
             for v in (max(1, native // 2), native, min(16, 2 * native)) for r in (1, 2, 4, 8)]
 
 
-# what tune_all can tune; "gemv_row" / "gemv_col" are the rows and cols GEMV kernels
-ALL_OPS = ("copy", "axpby", "dot", "nrm2", "cg", "gemv_row", "gemv_col", "ger")
+def _batch_candidates(quick):
+    # the work-group size and the packs of a GEMV row each lane of a staged
+    # tile owns (fewer packs: more lanes share a row)
+    return [dict(block=b, unroll=u) for b in ((256, 512) if quick else (128, 256, 512))
+            for u in ((8, 16) if quick else (4, 8, 16, 32))]
+
+
+# the uneven batch tuned on: 512 GEMVs with M, N log-uniform in [32, 4096] and
+# 4096 dots with n log-uniform in [1e3, 1e6], seed 0
+def _batch_sizes():
+    import workloads as W
+    return W.batched_sizes(0)
+
+
+# what tune_all can tune; "gemv_row" / "gemv_col" are the rows and cols GEMV
+# kernels, "batch" the batch plans
+ALL_OPS = ("copy", "axpby", "dot", "nrm2", "cg", "gemv_row", "gemv_col", "ger", "batch")
 
 
 def tune_all(dtypes=("f64", "f32", "bf16"), quick=False, log=print, ops_=ALL_OPS, vec_sizes=None,
-             gemv_shapes=None, ger_shapes=None, max_candidates=None, accs=("plain", "compensated")):
+             gemv_shapes=None, ger_shapes=None, max_candidates=None, accs=("plain", "compensated"),
+             batch_sizes=None):
     """Sweep every operation of `ops_`, storage type, accumulation mode (for
     the reducing operations, of `accs`) and size class; return the table
     entries and a report (best and default rates, copy proxy).  vec_sizes,
     gemv_shapes and ger_shapes replace the workloads tuned on;
     max_candidates keeps only the first candidates of each list (both for a
-    quick check of the tuner itself, not for a table)."""
+    quick check of the tuner itself, not for a table); batch_sizes (M[], N[],
+    D[]) replaces the uneven batch."""
     global _blocker
     _blocker = _Blocker()
     try:
         return _tune_all(dtypes, quick, log, ops_, vec_sizes or VEC_SIZES, gemv_shapes or GEMV_SHAPES,
-                         ger_shapes or ((4096, 4096), (16384, 16384)), max_candidates, accs)
+                         ger_shapes or ((4096, 4096), (16384, 16384)), max_candidates, accs,
+                         batch_sizes or _batch_sizes())
     finally:
         _blocker = None
 
 
-def _tune_all(dtypes, quick, log, ops_, vec_sizes, gemv_shapes, ger_shapes, max_candidates, accs):
+def _tune_all(dtypes, quick, log, ops_, vec_sizes, gemv_shapes, ger_shapes, max_candidates, accs, batch_sizes):
     cut = (lambda c: c[:max_candidates]) if max_candidates else (lambda c: c)
     cus = L.lib.bwla_device_cus()
     ops.reset_config()
@@ -476,6 +525,14 @@ def _tune_all(dtypes, quick, log, ops_, vec_sizes, gemv_shapes, ger_shapes, max_
             entries.append((L.OP_GER, dt, None, w.cls, res[0][0]))
             record(w, res, default_ms, dn=dn, m=m, n=n)
             del w
+        if "batch" in ops_:
+            for acc in accs:
+                w = Workload("batch", dt, m=batch_sizes, acc=acc)
+                default_ms = time_ms(w.run, reps=10)
+                res = sweep(w, cut(_batch_candidates(quick)), reps=6, refine=refine)
+                entries.append((L.OP_BATCH, dt, acc, w.cls, res[0][0]))
+                record(w, res, default_ms, dn=dn, gemvs=len(batch_sizes[0]), dots=len(batch_sizes[2]))
+                del w
     return entries, report
 
 

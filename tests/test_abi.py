@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version_and_strings(L):
-    assert L.lib.bwla_abi_version() == L.ABI_VERSION == 3
+    assert L.lib.bwla_abi_version() == L.ABI_VERSION == 4
     for st, name in [(0, b"ok"), (1, b"invalid argument"), (3, b"workspace too small"), (4, b"HIP error")]:
         assert L.lib.bwla_status_string(st) == name
 
@@ -91,7 +91,7 @@ def test_unknown_enum_values_are_rejected(L):
                 assert call(0, bad, 0) == L.ERR_UNSUPPORTED, (name, "acc", bad)
             if name in with_out:
                 assert call(0, 0, bad) in (L.ERR_UNSUPPORTED, L.ERR_INVALID_ARG), (name, "out type", bad)
-    for bad in (-2, 8, 99):
+    for bad in (-2, L.OP_COUNT, 99):
         assert lib.bwla_get_config(bad, 0, 0, 1, 1000, ctypes.byref(cfg)) == L.ERR_INVALID_ARG
         assert lib.bwla_set_config(bad, 0, 0, 1, None) == L.ERR_INVALID_ARG
     for bad in (3, 7, -1):
@@ -117,6 +117,27 @@ def test_unroll_limits(L):
         assert ops.get_config(L.OP_DOT, torch.float32, 0, 1 << 20)["unroll"] == 8
         ops.set_config(L.OP_AXPBY, torch.float32, -1, unroll=16)
         assert ops.get_config(L.OP_AXPBY, torch.float32, 0, 1 << 20)["unroll"] == 4
+    finally:
+        ops.reset_config()
+
+
+def test_batch_configuration_from_the_table(L):
+    """Batch plans take their work-group size and packs per lane from the
+    BWLA_OP_BATCH entry of the plan's size class (by algorithmic bytes);
+    defaults 256 threads and 16 packs; work-groups are capped at 512."""
+    import torch
+    from paper_1409_0669_amd import ops
+    try:
+        ops.reset_config()
+        got = ops.get_config(L.OP_BATCH, torch.float32, 0, 3 << 30)
+        assert (got["block"], got["unroll"]) == (256, 16)
+        ops.set_config(L.OP_BATCH, torch.float32, 4, acc="compensated", block=512, unroll=8)
+        got = ops.get_config(L.OP_BATCH, torch.float32, 0, 3 << 30, acc="compensated")
+        assert (got["block"], got["unroll"]) == (512, 8)
+        assert ops.get_config(L.OP_BATCH, torch.float32, 0, 3 << 30)["unroll"] == 16      # the other mode
+        assert ops.get_config(L.OP_BATCH, torch.float32, 0, 1 << 20, acc="compensated")["unroll"] == 16  # class
+        ops.set_config(L.OP_BATCH, torch.bfloat16, -1, block=1024)
+        assert ops.get_config(L.OP_BATCH, torch.bfloat16, 0, 3 << 30)["block"] == 512
     finally:
         ops.reset_config()
 

@@ -23,6 +23,25 @@ def _grouped(monkeypatch):
     monkeypatch.delenv("BWLA_ENABLE_UNVALIDATED_BATCH", raising=False)
 
 
+@pytest.mark.parametrize("packs", [1, 4, 32])
+def test_grouped_packs_per_lane(packs):
+    """The packs of a GEMV row each lane of a staged tile owns (the batch
+    table entry's unroll, here given to the plan): 1 puts up to 64 lanes on
+    a row, 32 few; every problem against the oracle."""
+    need_gpu()
+    from paper_1409_0669_amd.batch import BatchPlan
+    for dtype in ("f64", "f32", "bf16"):
+        guards = []
+        gemvs, dots = from_sizes(dtype, np.array([1, 9, 300, 64]), np.array([3, 1000, 4097, 257]),
+                                 np.array([5, 70001]), seed=5, align=1, guards=guards)
+        for acc in ("plain", "compensated"):
+            BatchPlan(gemvs, dots, acc=acc, packs=packs, block=512).run()
+            torch.cuda.synchronize()
+            check(dtype, acc, gemvs, dots)
+            for g in guards:
+                g()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("acc", ["plain", "compensated"])
 def test_grouped_matches_oracle(dtype, acc):

@@ -21,12 +21,14 @@ def test_tuner_smoke_writes_a_table_the_library_uses(tmp_path):
     from paper_1409_0669_amd import ops, tune
     ops.reset_config()
     try:
+        bsizes = (np.array([37, 300, 5]), np.array([1000, 64, 3000]), np.array([5000, 70000, 1]))
         entries, report = tune.tune_all(("f32",), quick=True, log=lambda *a: None,
-                                        ops_=("dot", "gemv_row", "gemv_col"), vec_sizes=(1 << 16, 1 << 18),
-                                        gemv_shapes=((512, 384),), max_candidates=2, accs=("plain",))
+                                        ops_=("dot", "gemv_row", "gemv_col", "batch"), vec_sizes=(1 << 16, 1 << 18),
+                                        gemv_shapes=((512, 384),), max_candidates=2, accs=("plain",),
+                                        batch_sizes=bsizes)
         kinds = {(op, cls) for op, _, _, cls, _ in entries}
         assert (L.OP_DOT, 0) in kinds and (L.OP_DOT, 1) in kinds
-        assert {op for op, _, _, _, _ in entries} == {L.OP_DOT, L.OP_GEMV_ROWS, L.OP_GEMV_COLS}
+        assert {op for op, _, _, _, _ in entries} == {L.OP_DOT, L.OP_GEMV_ROWS, L.OP_GEMV_COLS, L.OP_BATCH}
         assert all(r.get("best_gbs", r.get("best_gbs_geomean", 0)) > 0 for r in report["results"])
         path = str(tmp_path / "table.txt")
         tune.write_table(entries, path)
@@ -45,6 +47,17 @@ def test_tuner_smoke_writes_a_table_the_library_uses(tmp_path):
             xv, xv64 = vec(384, "f32", 1703)
             check_vector(host(ops.gemv(A, xv)), oracle.gemv(A64, xv64), np.abs(A64) @ np.abs(xv64), TOL["f32"],
                          "gemv " + layout)
+        # a batch plan built under the tuned batch entry
+        from paper_1409_0669_amd.batch import BatchPlan
+        from tests.batch_util import check, from_sizes
+        (bcfg,) = [cfg for op, _, _, _, cfg in entries if op == L.OP_BATCH]
+        gemvs, dots = from_sizes("f32", *bsizes, seed=4)
+        nbytes = BatchPlan(gemvs, dots).info()["bytes"]
+        got = ops.get_config(L.OP_BATCH, torch.float32, 0, int(nbytes))
+        assert (got["block"], got["unroll"]) == (bcfg["block"], bcfg["unroll"])
+        BatchPlan(gemvs, dots).run()
+        torch.cuda.synchronize()
+        check("f32", "plain", gemvs, dots)
     finally:
         ops.reset_config()
         ops.load_default_tuning()

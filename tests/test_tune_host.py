@@ -138,7 +138,7 @@ def test_shipped_table_has_both_accumulation_modes():
             assert len(line) == 11, line
             rows.append(tuple(int(v) for v in line))
     assert L.lib.bwla_load_tuning(tune.DEFAULT_TABLE.encode()) == L.OK
-    reducing = {L.OP_DOT, L.OP_NRM2, L.OP_CG, L.OP_GEMV_ROWS, L.OP_GEMV_COLS}
+    reducing = {L.OP_DOT, L.OP_NRM2, L.OP_CG, L.OP_GEMV_ROWS, L.OP_GEMV_COLS, L.OP_BATCH}
     keys = {(op, t, a, k) for op, t, a, k, *_ in rows}
     for op, t, a, k, *_ in rows:
         if op in reducing:
@@ -344,3 +344,17 @@ def test_time_ms_starts_each_interval_behind_the_blocker(monkeypatch):
     monkeypatch.setattr(tune, "_blocker", None)
     tune.time_ms(lambda: trace.append("call"), reps=1, warmup=0, batch=1)
     assert trace == ["record", "call", "record"]
+
+
+def test_batch_candidates_and_sizes():
+    """The batch plans are tuned over work-group sizes up to 512 (the plans'
+    limit) and packs per lane up to 32 (powers of two), on the uneven batch
+    of 512 GEMVs and 4096 dots."""
+    from paper_1409_0669_amd import tune
+    for quick in (False, True):
+        c = tune._batch_candidates(quick)
+        assert c and all(d["block"] <= 512 and d["block"] % 64 == 0 for d in c)
+        assert all(d["unroll"] in (1, 2, 4, 8, 16, 32) for d in c)
+    M, N, D = tune._batch_sizes()
+    assert len(M) == len(N) == 512 and len(D) == 4096
+    assert "batch" in tune.ALL_OPS
