@@ -220,7 +220,8 @@ __device__ __forceinline__ void gemv_tile_block(const BatchGemv &g, int64_t rb, 
 //
 // A row belongs to a group of G lanes (a compile-time constant here, so every
 // LDS and global offset within a trip is an immediate), G sized on the host
-// so that each lane owns about kStagedPacks packs of it.  One trip issues the
+// so that each lane owns about the plan's packs per lane (the batch table
+// entry's unroll, kStagedPacks by default) of it.  One trip issues the
 // U packs of A and their U*V x entries before any arithmetic; two
 // accumulators per lane split the dependency chain.  Loop control is
 // wave-uniform; rows past the tile re-read its last row and are not stored.

@@ -160,7 +160,7 @@ enum {
     kModeScalar = 2  // one element per access
 };
 constexpr int kTileStageBytes = 32768; // most LDS a staged GEMV tile's x may take
-constexpr int kStagedPacks = 16;       // packs of a row each lane of a staged tile owns (sets its row-group size)
+constexpr int kStagedPacks = 16;       // default packs of a row each lane of a staged tile owns (sets its row-group size)
 // Longest x a staged tile takes, for storage elements of `es` bytes: x is
 // held in the compute precision (8 bytes for f64, 4 otherwise) in V = 16/es
 // residue rows whose stride is at most ceil(n / V) + 64 words.
