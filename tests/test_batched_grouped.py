@@ -12,7 +12,7 @@ import torch
 import oracle
 import workloads as W
 from tests.batch_util import check, from_sizes, problems
-from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector
+from tests.criteria import TOL, bitwise_equal, check_scalar, check_vector, cond_scale, plain_reduced
 from tests.gpu_util import DT, host, need_gpu
 
 pytestmark = pytest.mark.gpu
@@ -21,6 +21,42 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(autouse=True)
 def _grouped(monkeypatch):
     monkeypatch.delenv("BWLA_ENABLE_UNVALIDATED_BATCH", raising=False)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_grouped_infinite_and_nan_entries(dtype):
+    """Batched GEMVs and dots whose data hold +-inf or NaN: those outputs are
+    the oracle's non-finite values bitwise (the compensation must not turn
+    inf into NaN), the others stay within tolerance."""
+    need_gpu()
+    from paper_1409_0669_amd.batch import BatchPlan
+    gemvs, dots = from_sizes(dtype, np.array([40, 7, 300]), np.array([500, 9000, 33]), np.array([70001, 5, 200000]),
+                             seed=6)
+    A0, _, _ = gemvs[0]
+    A0[3, 17] = float("inf")                    # row 3 of the first GEMV
+    A0[9, 2], A0[9, 400] = float("inf"), float("-inf")   # row 9: inf - inf
+    gemvs[2][1][5] = float("nan")               # x of the third GEMV: every row
+    dots[0][0][12345] = float("-inf")
+    dots[2][1][7] = float("nan")
+    for acc in ("plain", "compensated"):
+        BatchPlan(gemvs, dots, acc=acc).run()
+        torch.cuda.synchronize()
+        for i, (A, x, y) in enumerate(gemvs):
+            A64, x64 = host(A), host(x)
+            ref, got = oracle.gemv(A64, x64), host(y)
+            fin = np.isfinite(ref)
+            assert bitwise_equal(got[~fin], ref[~fin]), (acc, "gemv", i)
+            check_vector(got[fin], ref[fin], np.abs(A64[fin]) @ np.abs(x64), TOL[dtype], "gemv %d" % i,
+                         plain_f32=plain_reduced(dtype, acc))
+        for i, (p, q, out) in enumerate(dots):
+            p64, q64 = host(p), host(q)
+            check_scalar(float(out.item()), oracle.dot(p64, q64), cond_scale(dtype, acc, np.abs(p64 * q64).sum()),
+                         TOL[dtype], "%s dot %d" % (acc, i))
+        # the planted entries reached the outputs (signs follow the other factor)
+        assert not np.isfinite(float(dots[0][2].item())) and np.isnan(float(dots[2][2].item()))
+        y0 = host(gemvs[0][2])
+        assert not np.isfinite(y0[3]) and not np.isfinite(y0[9])
+        assert np.all(np.isnan(host(gemvs[2][2])))
 
 
 @pytest.mark.parametrize("packs", [1, 4, 32])

@@ -254,10 +254,19 @@ def test_sums_with_infinite_and_nan_entries(dtype, acc):
         check_scalar(float(ops.asum(x, acc=acc).item()), oracle.asum(x64), 0.0, TOL[dtype], "asum " + name)
         check_scalar(float(ops.nrm2(x, acc=acc).item()), oracle.nrm2(x64), 0.0, TOL[dtype], "nrm2 " + name)
         A = x[: 300 * 300].view(300, 300)
+        A64 = x64[: 300 * 300].reshape(300, 300)
         y = host(ops.gemv(A, ones[:300], acc=acc))
-        ref = oracle.gemv(x64[: 300 * 300].reshape(300, 300), np.ones(300))
+        ref = oracle.gemv(A64, np.ones(300))
         fin = np.isfinite(ref)
         assert bitwise_equal(y[~fin], ref[~fin]), name
+        # the transposed product reads the same bytes with the cols kernel
+        # (the special entry's column is non-finite)
+        yt = host(ops.gemv(A, ones[:300], trans=True, acc=acc))
+        reft = oracle.gemv(np.ascontiguousarray(A64.T), np.ones(300))
+        fin = np.isfinite(reft)
+        assert bitwise_equal(yt[~fin], reft[~fin]), name + " transposed"
+        check_vector(yt[fin], reft[fin], np.abs(A64.T[fin]) @ np.ones(300), TOL[dtype], name + " transposed",
+                     plain_f32=plain_reduced(dtype, acc))
 
 
 # ---------------------------------------------------------------------------
