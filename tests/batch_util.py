@@ -20,10 +20,11 @@ def problems(dtype, n_gemv, n_dot, gemv_hi, dot_hi, seed=0, align=64):
     return from_sizes(dtype, Ms, Ns, Ds, seed, align)
 
 
-def from_sizes(dtype, Ms, Ns, Ds, seed=0, align=64, guards=None):
+def from_sizes(dtype, Ms, Ns, Ds, seed=0, align=64, guards=None, od=None):
     """As problems(), from given sizes.  With a list ``guards``, every output
     sits between sentinel slack (tests.gpu_util.guarded) and the list
-    receives each output's check."""
+    receives each output's check.  ``od``: the output dtype (default float64
+    for f64 storage, else float32)."""
     def off(sizes):
         o, offs = 0, []
         for s in sizes:
@@ -37,7 +38,8 @@ def from_sizes(dtype, Ms, Ns, Ds, seed=0, align=64, guards=None):
     X = W.device_draw(x_tot, dtype, seed, 502)
     P = W.device_draw(d_tot, dtype, seed, 503)
     Q = W.device_draw(d_tot, dtype, seed, 504)
-    od = torch.float64 if dtype == "f64" else torch.float32
+    if od is None:
+        od = torch.float64 if dtype == "f64" else torch.float32
     gemvs = []
     for i, (m, n) in enumerate(zip(Ms, Ns)):
         m, n = int(m), int(n)

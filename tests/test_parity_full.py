@@ -168,3 +168,63 @@ def test_gemv_beyond_int32_elements():
         cols = np.stack([host(A[:, int(j)].contiguous()) for j in idx])
         check_vector(yt[idx], oracle.gemv(cols, x64), np.abs(cols) @ np.abs(x64), TOL["f32"], "cols " + acc)
     del A
+
+
+def test_ger_beyond_int32_elements():
+    """The rank-1 overwrite A = u v^T on 46341 x 46341 float32 entries (more
+    than a 32-bit index holds), row-major and then column-major over the same
+    bytes: sampled rows and columns, the last ones included, bitwise against
+    the oracle's once-rounded products."""
+    from paper_1409_0669_amd import ops
+    m = 46341
+    u = W.device_draw(m, "f32", 0, 720)
+    v = W.device_draw(m, "f32", 0, 721)
+    u64, v64 = host(u), host(v)
+    rng = np.random.default_rng(6)
+    idx = np.unique(np.concatenate([[0, 1, m // 2, m - 2, m - 1], rng.integers(0, m, 12)]))
+    A = torch.full((m, m), float("nan"), dtype=torch.float32, device="cuda")
+    for layout in ("row", "col"):
+        view = A if layout == "row" else A.t()    # the transpose of a contiguous A is column-major
+        ops.ger(u, v, view)
+        for i in idx:
+            i = int(i)
+            assert bitwise_equal(host(view[i]), oracle.ger("f32", u64[i:i + 1], v64)), (layout, "row", i)
+            assert bitwise_equal(host(view[:, i]), oracle.ger("f32", u64, v64[i:i + 1])), (layout, "col", i)
+    del A
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+def test_batch_beyond_int32_elements(acc):
+    """One batch plan holding a 46341 x 46341 float32 GEMV and a dot of
+    2^31 + 37 elements (both past a 32-bit index) beside small uneven
+    problems: the GEMV on sampled outputs against the oracle on those rows,
+    the long dot <1, 1> against its closed form (every chunk partial is an
+    exact count and the chunk combine is exact), the small problems in
+    full."""
+    from paper_1409_0669_amd.batch import BatchPlan
+    from tests.batch_util import check, from_sizes
+    m, nd = 46341, (1 << 31) + 37
+    A = W.device_draw(m * m, "f32", 0, 730).view(m, m)
+    x = W.device_draw(m, "f32", 0, 731)
+    ones = torch.ones(nd, dtype=torch.float32, device="cuda")
+    y = torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+    out = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+    guards = []
+    gemvs, dots = from_sizes("f32", np.array([37, 300, 5]), np.array([1000, 64, 3000]),
+                             np.array([5000, 70000, 1]), seed=7, guards=guards, od=torch.float64)
+    plan = BatchPlan(gemvs + [(A, x, y)], dots + [(ones, ones, out)], acc=acc, out_dtype=torch.float64)
+    plan.run()
+    torch.cuda.synchronize()
+    check("f32", acc, gemvs, dots)
+    for g in guards:
+        g()
+    assert float(out.item()) == nd
+    x64, yh = host(x), host(y)
+    rng = np.random.default_rng(8)
+    idx = np.unique(np.concatenate([[0, 1, m // 2, m - 2, m - 1], rng.integers(0, m, 12)]))
+    rows = np.stack([host(A[int(i)]) for i in idx])
+    check_vector(yh[idx], oracle.gemv(rows, x64), np.abs(rows) @ np.abs(x64), TOL["f32"], "gemv " + acc,
+                 plain_f32=plain_reduced("f32", acc))
+    assert np.all(np.isfinite(yh))
+    plan.close()
+    del A, ones
