@@ -228,3 +228,39 @@ def test_batch_beyond_int32_elements(acc):
     assert np.all(np.isfinite(yh))
     plan.close()
     del A, ones
+
+
+def test_strided_beyond_int32_offsets():
+    """Increments that carry element offsets past a 32-bit index: n = 2^30 + 3
+    logical elements at increments 2 and -2 span 2^31 + 5 stored elements.
+    The strided dot of ones against its closed form n (float64 output: the
+    per-thread partials are exact counts and their combine is exact), and a
+    strided axpby into increment -2 checked bitwise on sampled logical
+    indices, the first and last included."""
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    n = (1 << 30) + 3
+    span = 2 * (n - 1) + 1
+    ws = ops._ws_ptr(ops.workspace(ops.workspace_size(L.OP_DOT, torch.float32, n=n), torch.device("cuda")))
+    ones = torch.ones(span, dtype=torch.float32, device="cuda")
+    out = torch.full((), float("nan"), dtype=torch.float64, device="cuda")
+    for acc in (L.ACC_PLAIN, L.ACC_COMPENSATED):
+        L.check(L.lib.bwla_dot_strided(L.F32, acc, n, ones.data_ptr(), 2, ones.data_ptr(), -2, L.F64,
+                                       out.data_ptr(), *ws, ops._stream()))
+        assert float(out.item()) == n, acc
+    del ones
+    y = W.device_draw(span, "f32", 0, 740)
+    z = W.device_draw(n, "f32", 0, 741)
+    x = torch.full((span,), float("nan"), dtype=torch.float32, device="cuda")
+    a, b = 0.75, -1.25
+    L.check(L.lib.bwla_axpby_strided(L.F32, n, a, None, y.data_ptr(), 2, b, None, z.data_ptr(), 1, x.data_ptr(), -2,
+                                     ops._stream()))
+    rng = np.random.default_rng(9)
+    i = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, 4096)]))
+    ti = torch.from_numpy(i).cuda()
+    ys, zs, xs = host(y[2 * ti]), host(z[ti]), host(x[2 * (n - 1 - ti)])
+    ref = oracle.axpby("f32", oracle.scalar("f32", a), ys, oracle.scalar("f32", b), zs)
+    assert bitwise_equal(xs, ref)
+    # the gaps between the strided outputs are untouched
+    gaps = host(x[2 * torch.from_numpy(np.unique(np.minimum(i, n - 2))).cuda() + 1])
+    assert np.all(np.isnan(gaps))
