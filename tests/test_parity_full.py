@@ -264,3 +264,52 @@ def test_strided_beyond_int32_offsets():
     # the gaps between the strided outputs are untouched
     gaps = host(x[2 * torch.from_numpy(np.unique(np.minimum(i, n - 2))).cuda() + 1])
     assert np.all(np.isnan(gaps))
+
+
+@pytest.mark.parametrize("acc", ["plain", "compensated"])
+def test_cg_update_beyond_int32_elements(acc):
+    """The fused update x += a p, r -= a q, <r, r> on bf16 vectors of
+    2^31 + 37 elements: x and p drawn at random and x checked bitwise on
+    sampled indices (the tail included); r = 2, q = 1 and a = 1 make every
+    updated r_i exactly 1, so <r, r> is the count n (float64 output; exact
+    counts throughout)."""
+    from paper_1409_0669_amd import ops
+    n = (1 << 31) + 37
+    x = W.device_draw(n, "bf16", 0, 750)
+    p = W.device_draw(n, "bf16", 0, 751)
+    r = torch.full((n,), 2.0, dtype=torch.bfloat16, device="cuda")
+    q = torch.ones(n, dtype=torch.bfloat16, device="cuda")
+    rng = np.random.default_rng(10 + (acc == "compensated"))
+    idx = np.unique(np.concatenate([np.arange(8), rng.integers(0, n, 4096), np.arange(n - 64, n)]))
+    ti = torch.from_numpy(idx).cuda()
+    x0, p0 = host(x[ti]), host(p[ti])
+    rr = float(ops.cg_update(1.0, x, p, r, q, acc=acc, out_dtype=torch.float64).item())
+    assert rr == n
+    ae = oracle.scalar("bf16", 1.0)
+    assert bitwise_equal(host(x[ti]), oracle.axpby("bf16", ae, p0, 1.0, x0))
+    assert bitwise_equal(host(r[ti]), np.ones(idx.size))
+    del x, p, r, q
+
+
+@pytest.mark.parametrize("lda", [(1 << 31) + 64, (1 << 31) + 7])
+def test_gemv_leading_dimension_beyond_int32(lda):
+    """Three rows of 1000 float32 entries lda = 2^31 + 64 (16-byte packs) or
+    2^31 + 7 (one element per access) apart: row offsets pass a 32-bit
+    index.  y = A x (rows kernel) and y = A^T v (cols kernel) on every output
+    against the oracle."""
+    from paper_1409_0669_amd import ops
+    m, n = 3, 1000
+    buf = torch.full(((m - 1) * lda + n,), float("nan"), dtype=torch.float32, device="cuda")
+    A = buf.as_strided((m, n), (lda, 1))
+    A.copy_(W.device_draw(m * n, "f32", 0, 760).view(m, n))
+    x = W.device_draw(n, "f32", 0, 761)
+    v = W.device_draw(m, "f32", 0, 762)
+    A64 = np.stack([host(A[i]) for i in range(m)])
+    x64, v64 = host(x), host(v)
+    for acc in ("plain", "compensated"):
+        check_vector(host(ops.gemv(A, x, acc=acc)), oracle.gemv(A64, x64), np.abs(A64) @ np.abs(x64), TOL["f32"],
+                     "rows " + acc, plain_f32=plain_reduced("f32", acc))
+        At = np.ascontiguousarray(A64.T)
+        check_vector(host(ops.gemv(A, v, trans=True, acc=acc)), oracle.gemv(At, v64), np.abs(At) @ np.abs(v64),
+                     TOL["f32"], "cols " + acc, plain_f32=plain_reduced("f32", acc))
+    del buf, A
