@@ -430,8 +430,8 @@ def _replay_ms(torch, g, reps):
 
 
 def batched_rows(torch, W, ops, reps):
-    """The uneven batch three ways: the batched plan (one launch, one
-    work-group per work item) launched directly and replayed from its HIP
+    """The uneven batch three ways: the batched plan (one launch per kind of
+    work item, one work-group per item) launched directly and replayed from its HIP
     graph, and -- as the baseline it replaces -- one library call per problem,
     all captured in one HIP graph."""
     from paper_1409_0669_amd.batch import BatchPlan
@@ -441,7 +441,7 @@ def batched_rows(torch, W, ops, reps):
         plan = BatchPlan(gemvs, [(p, q, r) for p, q, r in dots], acc="compensated")
         ms = _median_ms(torch, plan.run, reps)
         info = plan.info()
-        out["batched %s compensated, one launch (%d items)" % (dt, info["items"])] = {
+        out["batched %s compensated, one plan run (%d items)" % (dt, info["items"])] = {
             "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 3), "bytes": int(nbytes)}
         cap = torch.cuda.Stream()
         plan.capture(cap)

@@ -311,18 +311,19 @@ bwla_status bwla_cg_update(bwla_dtype t, bwla_acc acc, int64_t n, double alpha,
 bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_layout layout,
                                 int trans, int64_t m, int64_t n, size_t *bytes);
 
-/* ---- batched uneven problems in one launch -------------------------------
+/* ---- batched uneven problems ---------------------------------------------
  * A plan holds many row-major GEMVs (y = A x, out_t output) and many dots
  * (out = <x, y>, out_t output) of one storage type.  Work is flattened into
  * items (row tiles of a GEMV, chunks of a dot) ordered largest first and run
- * in one launch with one work-group per item (the hardware dispatcher hands
- * out the items in order).  Each dot's chunk partials are combined in chunk
+ * with one work-group per item, one launch per kind of item (GEMV tiles with
+ * x staged in LDS, the other GEMV tiles, dot chunks; the hardware dispatcher
+ * hands out each launch's items in order).  Each dot's chunk partials are combined in chunk
  * order by a finalize kernel, so results do not depend on the batch order or
  * on scheduling.
  * create: copies the descriptors to the device and allocates the plan's own
  *         counters and partial slots (the only allocating call; not allowed
  *         while `stream` capture is active).
- * run:    enqueues the batched kernel and the dot finalize kernel.
+ * run:    enqueues the batched kernels and the dot finalize kernel.
  * capture: records the same kernels into a HIP graph owned by the plan.
  * replay: launches the captured graph.
  * Descriptor pointers must stay valid while the plan is used.

@@ -3,7 +3,7 @@
 The operations of Rupp et al., "Performance Portability Study of Linear Algebra
 Kernels in OpenCL" (IWOCL 2014), Section 2 -- vector copy, scaled vector
 addition, inner product and dense matrix-vector product -- plus the Euclidean
-norm, gradients, one launch for a batch of uneven problems, fused composites
+norm, gradients, batch plans for many uneven problems, fused composites
 (a CG-style update, GEMV with an inner-product epilogue) and a BLAS-style
 interface (increments, scal, asum, alpha/beta GEMV), as hand-written HIP
 kernels behind the C ABI in ``include/bwla.h``.
@@ -14,7 +14,8 @@ Submodules (imported on first use; importing them fails loudly when
 * ``ops``       tensor-level calls (copy, axpby, scal, dot, nrm2, asum, gemv,
                 gemv_dot, ger, cg_update)
 * ``autograd``  ``GemvFn`` and ``DotFn`` with hand-written backward kernels
-* ``batch``     ``BatchPlan``: many uneven GEMVs and dots in one launch / HIP graph
+* ``batch``     ``BatchPlan``: many uneven GEMVs and dots, one launch per kind of
+                work item, replayable from a HIP graph
 * ``tune``      the autotuner and the configuration-space study
 * ``build``     compiles the library with hipcc
 """

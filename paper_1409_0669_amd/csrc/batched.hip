@@ -1,4 +1,4 @@
-// batched.hip -- many uneven row-major GEMVs and dots in one launch.
+// batched.hip -- many uneven row-major GEMVs and dots, batched.
 //
 // Two designs share the work-item list.  The grouped launch (k_grouped_gemv
 // and k_grouped_dot, below the persistent kernel) runs one work-group per
