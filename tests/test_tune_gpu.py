@@ -61,3 +61,37 @@ def test_tuner_smoke_writes_a_table_the_library_uses(tmp_path):
     finally:
         ops.reset_config()
         ops.load_default_tuning()
+
+
+def test_configuration_study_on_a_small_space(monkeypatch):
+    """The configuration study end to end on the GPU, over a few
+    configurations of each space and small sizes: it times every operation
+    in every configuration, analyses the rates into the report (distributions,
+    copy against the other operations, the single-configuration comparison,
+    the GEMV part) and renders it; the shipped table is restored after."""
+    need_gpu()
+    from paper_1409_0669_amd import ops, study, tune
+    vfull, rfull = tune.vector_space, tune.rows_space
+    vsub = lambda cus: vfull(cus)[::150]
+    rsub = lambda: [c for c in rfull() if c["block"] == 256 and c["unroll"] == 1 and c["split"] in (1, 2)
+                    and c["rows"] in (1, 4)]
+    monkeypatch.setattr(tune, "vector_space", vsub)
+    monkeypatch.setattr(tune, "rows_space", rsub)
+    monkeypatch.setattr(study, "GEMV_SIZES", {"200000": 512})
+    try:
+        res = study.run(sizes=(200_000,), reps=2, log=lambda *a: None)
+    finally:
+        ops.reset_config()
+        ops.load_default_tuning()
+    rep = res["sizes"]["200000"]
+    assert rep["n_configs"] == len(vsub(res["cus"]))
+    for op in study.OPS:
+        t = rep["table2"][op]
+        assert 0 < t["with_copy_cfg"] <= t["own_best"]
+        assert t["tie_penalty_pct"]["min"] >= 0
+    assert set(rep["copy_vs_ops"]) == set(study.OPS[1:])
+    g = rep["gemv"]
+    assert g["m"] == 512 and g["n_configs"] == len(rsub())
+    assert 0 < g["one_row_per_group_best"] <= g["own_best"]
+    md = study.markdown(res)
+    assert "200000" in md
