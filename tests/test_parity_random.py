@@ -304,3 +304,41 @@ def test_random_cg_update(case):
     assert bitwise_equal(host(x), oracle.axpby(dtype, ae, p64, 1.0, x64)), what
     assert bitwise_equal(host(r), rref), what
     check_scalar(rr, oracle.dot(rref, rref), 0.0, TOL[dtype], what)
+
+
+@pytest.mark.parametrize("case", range(100))
+def test_random_misaligned_unit_stride(case):
+    """Unit-stride vectors that start anywhere in their allocations (0 to 7
+    elements past a 256-byte boundary, independently per operand) under
+    random configurations: the pack width then falls back per call.  copy,
+    axpby and scal_to bitwise, dot and nrm2 within the criteria, and the
+    guard entries around the output untouched."""
+    from paper_1409_0669_amd import _lib as L
+    from paper_1409_0669_amd import ops
+    rng = _rng(10, case)
+    dtype, acc = _pick(rng, DTYPES), _pick(rng, ACCS)
+    n = _logint(rng, 1, 1_000_000)
+    oy, oz, ox = (int(rng.integers(0, 8)) for _ in range(3))
+    ecfg, rcfg = _vec_cfg(rng, False), _vec_cfg(rng, True)
+    a, b = float(rng.uniform(-2, 2)), float(rng.uniform(-2, 2))
+    what = "case %d: %s %s n=%d offsets y=%d z=%d x=%d elem=%s red=%s" % (case, dtype, acc, n, oy, oz, ox, ecfg, rcfg)
+    for op in (L.OP_AXPBY, L.OP_COPY):
+        ops.set_config(op, DT[dtype], -1, **ecfg)
+    for op in (L.OP_DOT, L.OP_NRM2):
+        ops.set_config(op, DT[dtype], -1, **rcfg)
+    y, y64 = vec(n, dtype, 110 + case % 5, pad_front=oy)
+    z, z64 = vec(n, dtype, 115 + case % 5, pad_front=oz)
+    buf = torch.full((n + ox + 8,), float("nan"), dtype=DT[dtype], device="cuda")
+    x = buf[ox:ox + n]
+    ops.axpby(a, y, b, z, out=x)
+    ref = oracle.axpby(dtype, oracle.scalar(dtype, a), y64, oracle.scalar(dtype, b), z64)
+    assert bitwise_equal(host(x), ref), what
+    ops.copy(z, out=x)
+    assert bitwise_equal(host(x), z64), what
+    ops.scal_to(a, y, out=x)
+    assert bitwise_equal(host(x), oracle.scal(dtype, oracle.scalar(dtype, a), y64)), what
+    rest = torch.cat([buf[:ox], buf[ox + n:]])
+    assert bool(torch.isnan(rest).all()), what
+    check_scalar(float(ops.dot(y, z, acc=acc).item()), oracle.dot(y64, z64),
+                 cond_scale(dtype, acc, np.abs(y64 * z64).sum()), TOL[dtype], "dot " + what)
+    check_scalar(float(ops.nrm2(y, acc=acc).item()), oracle.nrm2(y64), 0.0, TOL[dtype], "nrm2 " + what)
