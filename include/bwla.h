@@ -317,9 +317,9 @@ bwla_status bwla_workspace_size(bwla_op op, bwla_dtype t, bwla_acc acc, bwla_lay
  * items (row tiles of a GEMV, chunks of a dot) ordered largest first and run
  * with one work-group per item, one launch per kind of item (GEMV tiles with
  * x staged in LDS, the other GEMV tiles, dot chunks; the hardware dispatcher
- * hands out each launch's items in order).  Each dot's chunk partials are combined in chunk
- * order by a finalize kernel, so results do not depend on the batch order or
- * on scheduling.
+ * hands out each launch's items in order).  Each dot's chunk partials are
+ * combined in chunk order by a finalize kernel, so results do not depend on
+ * the batch order or on scheduling.
  * create: copies the descriptors to the device and allocates the plan's own
  *         counters and partial slots (the only allocating call; not allowed
  *         while `stream` capture is active).
