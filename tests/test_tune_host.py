@@ -358,3 +358,35 @@ def test_batch_candidates_and_sizes():
     M, N, D = tune._batch_sizes()
     assert len(M) == len(N) == 512 and len(D) == 4096
     assert "batch" in tune.ALL_OPS
+
+
+def test_shipped_table_entries_come_from_the_committed_tuner_reports():
+    """Every line of the shipped table is the class entry of a committed
+    tuner run: the cols GEMV from its re-tune report, the batch plans from
+    the batch report, every other operation from the full report."""
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    names = {0: "copy", 1: "axpby", 2: "dot", 3: "gemv_row", 4: "gemv_col", 5: "ger", 6: "nrm2", 7: "cg",
+             8: "batch"}
+    dts = {0: "f64", 1: "f32", 2: "bf16"}
+    reports = {}
+    for key, fname in (("full", "tuner_report_gfx950.json"), ("cols", "tuner_report_cols_gfx950.json"),
+                       ("batch", "tuner_report_batch_gfx950.json")):
+        with open(os.path.join(root, "results", fname)) as f:
+            reports[key] = json.load(f)["results"]
+    checked = 0
+    with open(os.path.join(root, "paper_1409_0669_amd", "tuning", "gfx950.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            op, t, acc, cls, block, vec, unroll, grid, inc, rows, split = map(int, line.split())
+            src = "cols" if op == 4 else "batch" if op == 8 else "full"
+            acc_name = {-1: None, 0: "plain", 1: "compensated"}[acc]
+            recs = [e for e in reports[src] if e["op"] == names[op] and e["dtype"] == dts[t] and e["class"] == cls
+                    and (acc_name is None or e.get("acc") in (acc_name, None))]
+            assert recs, line
+            want = recs[0].get("class_entry") or recs[0]["best"]
+            got = dict(block=block, vec=vec, unroll=unroll, grid=grid, increment=inc, rows=rows, split=split)
+            assert all(got[k] == v for k, v in want.items() if k in got), (line, want)
+            checked += 1
+    assert checked >= 140
